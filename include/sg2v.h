@@ -1,0 +1,224 @@
+/*
+ * sg2v -- colour-coding tree-template counting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libsg2v.so.  It implements the decoupled dynamic
+ * programme of SubGraph2Vec (Zhang et al., arXiv 2009.11665): for every
+ * colouring of the graph and every split of the template into an active and
+ * a passive sub-template, a neighbour aggregation B = A_G M_p (Sec. 4.1,
+ * Alg. 4, Eq. 1) followed by an element-wise multiply-add of B with the
+ * active table through colour-set split tables (Sec. 4.3, Alg. 5).  The
+ * colourful count of each colouring is scaled by 1/(P alpha) (Alg. 1).
+ *
+ * Conventions
+ *  - Every function returns an sg2v_status; 0 is success.  On failure the
+ *    thread-local message of sg2v_last_error() says why.  No C++ exception
+ *    crosses this interface.
+ *  - Handles are opaque.  A handle is used from one host thread at a time.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Device work is enqueued on it; functions returning host results
+ *    synchronise that stream before returning.
+ *  - The caller owns every buffer it passes.  Host buffers are read during
+ *    the call only; device buffers borrowed by a handle (see
+ *    SG2V_GRAPH_DEVICE_PTRS) must outlive the handle.
+ *  - Colours are 0..k-1 (Sec. 2.2.2).  A colour set C of size m has column
+ *    index I_C = sum_i binom(c_i, i) over its sorted elements c_1 < ... < c_m
+ *    (colexicographic rank; Table 1 leaves the index map open).
+ */
+#ifndef SG2V_H
+#define SG2V_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sg2v_status;
+#define SG2V_OK 0
+#define SG2V_EINVAL (-1)   /* null pointer, bad size, bad flag */
+#define SG2V_ENOTTREE (-2) /* parent array is not one rooted tree */
+#define SG2V_ERANGE (-3)   /* k < t, k > SG2V_KMAX, n or nnz out of range */
+#define SG2V_ENOMEM (-4)   /* device or host allocation failed, or budget too small */
+#define SG2V_EGRAPH (-5)   /* CSR malformed: unsorted row, duplicate, loop, asymmetric */
+#define SG2V_EDEVICE (-6)  /* a HIP call failed */
+
+#define SG2V_KMAX 20
+
+/* Arithmetic of the count tables. */
+typedef int32_t sg2v_mode;
+#define SG2V_FP64 0  /* IEEE double tables */
+#define SG2V_FP32S 1 /* float mantissas with a power-of-two exponent per column;
+                        final vertex reduction in double */
+#define SG2V_U64 2   /* unsigned 64-bit, exact modulo 2^64; overflow is flagged */
+
+typedef struct sg2v_plan sg2v_plan;
+typedef struct sg2v_graph sg2v_graph;
+typedef struct sg2v_colorings sg2v_colorings;
+
+/* Last error message of the calling thread ("" if none). */
+const char *sg2v_last_error(void);
+
+/* Library version string. */
+const char *sg2v_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Template plan (Sec. 2.3.2: template partitioning; Table 1: colour-set     */
+/* column index).                                                            */
+
+/* Build the partition of a tree template T with t = |V_T| vertices for k
+ * colours.  parent[v] is the parent of v and exactly one entry is -1 (the root
+ * rho).  Each sub-template T_s is split by cutting the edge from its root to
+ * its last child (children in increasing vertex order): the active child
+ * keeps the root, the passive child is the cut-off subtree.  Rooted
+ * sub-templates that are isomorphic share one table.  Split index tables
+ * (for every output colour set, its (active set, passive set) pairs), the
+ * automorphism count alpha and the colourful probability P are computed here.
+ *   parent : host, t entries, copied.
+ *   t      : 1 <= t <= k.
+ *   k      : t <= k <= SG2V_KMAX.
+ * Errors: EINVAL (null), ENOTTREE (not one tree), ERANGE (t, k). */
+sg2v_status sg2v_plan_create(const int32_t *parent, int32_t t, int32_t k, sg2v_plan **out);
+void sg2v_plan_destroy(sg2v_plan *plan);
+
+typedef struct {
+  int32_t t;              /* template vertices */
+  int32_t k;              /* colours */
+  int32_t n_nodes;        /* distinct rooted sub-templates, single vertex included */
+  int32_t n_splits;       /* distinct sub-templates with more than one vertex */
+  int32_t n_passive;      /* distinct passive children (one neighbour aggregation each) */
+  int32_t root_node;      /* node id of T itself */
+  int64_t alpha;          /* |Aut(T)| */
+  double colorful_prob;   /* P = k!/((k-t)! k^t) */
+  int64_t spmm_columns;   /* sum over distinct passives of C(k, |T_p|) */
+  int64_t pairs_per_vertex; /* sum over splits of C(k,|T_s|) C(|T_s|,|T_a|) */
+  int64_t widest_table;   /* max over nodes of C(k, |T_s|) */
+} sg2v_plan_info_t;
+
+sg2v_status sg2v_plan_info(const sg2v_plan *plan, sg2v_plan_info_t *out);
+
+typedef struct {
+  int32_t size;       /* |T_s| */
+  int32_t active;     /* node id of T_{s,a}, -1 for a single vertex */
+  int32_t passive;    /* node id of T_{s,p}, -1 for a single vertex */
+  int32_t vertex;     /* template vertex that roots the first occurrence */
+  int32_t n_kept;     /* number of that vertex's first children it keeps */
+  int32_t is_passive; /* 1 if some split uses this node as passive child */
+  int64_t columns;    /* C(k, size) */
+} sg2v_node_info_t;
+
+sg2v_status sg2v_plan_node(const sg2v_plan *plan, int32_t node, sg2v_node_info_t *out);
+
+/* Split index table of a node with more than one vertex (Alg. 5: every way of
+ * dividing C_s into an active and a passive colour set): out receives, for every output
+ * column I_s in increasing order, C(|T_s|, |T_a|) pairs (I_a, I_p) as int32,
+ * i.e. C(k,|T_s|) * C(|T_s|,|T_a|) * 2 values, host memory owned by the caller. */
+sg2v_status sg2v_plan_pairs(const sg2v_plan *plan, int32_t node, int32_t *out);
+
+/* ------------------------------------------------------------------------ */
+/* Graph (Table 1: A_G as a 0/1 -- or weighted -- sparse matrix in CSR).      */
+
+#define SG2V_GRAPH_DEVICE_PTRS 1u /* row_ptr/col_idx/w are device pointers, borrowed */
+#define SG2V_GRAPH_VALIDATE 2u    /* check sorted rows, no loops/duplicates, symmetry */
+
+/* Register an undirected graph as symmetric CSR with n vertices and nnz
+ * directed entries (each undirected edge appears as (i,j) and (j,i)).
+ *   row_ptr : n+1 int64, row_ptr[0] = 0, row_ptr[n] = nnz.
+ *   col_idx : nnz int32 in [0, n).
+ *   w       : nullable; nnz float edge weights A_G(i,j) (equal on both
+ *             directed entries of an edge).  NULL means A_G is 0/1.
+ * Host arrays are copied to the device on `stream`.  With DEVICE_PTRS the
+ * handle borrows the caller's device arrays.  Rows are grouped by degree for
+ * load balance on the device.
+ * Errors: EINVAL, ERANGE (n >= 2^31 or nnz < 0), EGRAPH (VALIDATE), EDEVICE. */
+sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *row_ptr,
+                              const int32_t *col_idx, const float *w, uint32_t flags,
+                              void *stream, sg2v_graph **out);
+void sg2v_graph_destroy(sg2v_graph *g);
+
+/* ------------------------------------------------------------------------ */
+/* Random colourings (Sec. 2.3.1; Alg. 5: colour every vertex per iteration). */
+
+/* Colour all n vertices for colourings first .. first+n_colorings-1 on the
+ * device.  Colour of vertex v in colouring j:
+ *   h = F(seed ^ F((j << 40) | v)),  colour = (hi32(h) * k) >> 32,
+ * F = SplitMix64's output finaliser (Steele, Lea & Flood 2014).  The paper
+ * leaves the generator open.  Requires n < 2^40, first + n_colorings < 2^24.
+ * Storage: n_colorings x n bytes on the device, colouring-major. */
+sg2v_status sg2v_color(const sg2v_graph *g, int32_t k, uint64_t seed, int32_t first,
+                       int32_t n_colorings, void *stream, sg2v_colorings **out);
+void sg2v_colorings_destroy(sg2v_colorings *c);
+
+/* Copy colourings to the host: out has n_colorings * n bytes. */
+sg2v_status sg2v_colorings_download(const sg2v_colorings *c, uint8_t *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Counting (Alg. 1 / Alg. 5).                                                */
+
+/* For every colouring j of `c`, run the dynamic programme for `plan` on `g`
+ * and return
+ *   colorful[j] = sum_i sum_{|C| = t} M_0(i, I_C)   (colourful labelled maps)
+ *   estimate[j] = colorful[j] / (P alpha)           (finalCount of Alg. 1)
+ *   *mean_estimate = average of estimate over j.
+ * colorful_u64 (nullable): the exact count modulo 2^64, SG2V_U64 mode only.
+ * overflow (nullable): set to 1 if a U64 intermediate exceeded 2^64 - 1.
+ * All output pointers are host pointers with n_colorings entries (nullable).
+ * Colourings are processed in batches: several colourings become extra
+ * columns of the same tables so that each pass over A_G serves all of them.
+ * Errors: EINVAL (k of c differs from the plan's, U64 with weights),
+ *         ENOMEM, EDEVICE. */
+sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
+                       sg2v_mode mode, void *stream, double *colorful, uint64_t *colorful_u64,
+                       double *estimate, double *mean_estimate, int32_t *overflow);
+
+/* Several templates over n_colorings colourings each (colourings
+ * seed-derived per plan: sg2v_color(g, k_p, seed, 0, n_colorings)), run as
+ * one captured device graph.  colorful/estimate: n_plans x n_colorings,
+ * plan-major, host.  Errors as sg2v_count. */
+sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n_plans,
+                             const sg2v_graph *g, uint64_t seed, int32_t n_colorings,
+                             sg2v_mode mode, void *stream, double *colorful, double *estimate);
+
+/* Reverse-mode derivative of f = sum_j grad_colorful[j] * colorful[j] with
+ * respect to every directed CSR weight A_G(i,j) (entry e of col_idx):
+ *   grad_w[e] = df / dA_G(i,j).
+ * The derivative with respect to the weight of an undirected edge is the sum
+ * over its two directed entries.  Tables of each split are recomputed during
+ * the backward sweep instead of being stored.
+ *   grad_colorful : host, n_colorings doubles.
+ *   grad_w        : device, nnz floats (FP32S) or doubles (FP64), written.
+ * mode: SG2V_FP64 or SG2V_FP32S.  Errors: EINVAL, ENOMEM, EDEVICE. */
+sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
+                            sg2v_mode mode, const double *grad_colorful, void *grad_w,
+                            void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Inspection (tests).                                                         */
+
+/* Compute the table of `node` (kind 0: M_s; kind 1: B = A_G M_s, node must be
+ * a passive child) for colouring `which` of `c` and copy it to the host as
+ * doubles (FP64, FP32S with the column exponent applied) or uint64 (U64),
+ * row-major n x C(k, |T_s|). */
+sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph *g,
+                             const sg2v_colorings *c, sg2v_mode mode, int32_t which,
+                             int32_t node, int32_t kind, void *host_out, void *stream);
+
+/* Tuning knobs (0 = automatic).  spmm_width: columns per SpMM chunk;
+ * ema_rows: rows per eMA tile; batch: colourings per pass; budget_bytes:
+ * device memory the count may use. */
+typedef struct {
+  int32_t spmm_width;
+  int32_t ema_rows;
+  int32_t batch;
+  int32_t reserved;
+  int64_t budget_bytes;
+} sg2v_tuning_t;
+
+sg2v_status sg2v_set_tuning(const sg2v_tuning_t *t);
+sg2v_status sg2v_get_tuning(sg2v_tuning_t *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG2V_H */

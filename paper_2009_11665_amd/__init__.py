@@ -1,0 +1,310 @@
+"""Python binding of libsg2v (colour-coding tree counting on MI355X).
+
+Argument marshalling only: every step of the count runs in the HIP kernels of
+``libsg2v.so``.  PyTorch provides device memory and the current stream.  If
+the library is missing the import of the native handle fails loudly; there is
+no CPU fallback.
+
+The functions mirror the C ABI of ``include/sg2v.h``:
+``Plan`` (sg2v_plan_*), ``Graph`` (sg2v_graph_*), ``Colorings``
+(sg2v_color), ``count`` (sg2v_count), ``count_batch``, ``count_grad`` and
+``debug_table``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsg2v.so")
+
+FP64 = 0
+FP32S = 1
+U64 = 2
+MODES = {"fp64": FP64, "fp32s": FP32S, "u64": U64}
+
+GRAPH_DEVICE_PTRS = 1
+GRAPH_VALIDATE = 2
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTTREE", -3: "ERANGE", -4: "ENOMEM", -5: "EGRAPH",
+           -6: "EDEVICE"}
+
+_lib = None
+
+
+class Sg2vError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        self.status = status
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("k", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+                ("n_splits", ctypes.c_int32), ("n_passive", ctypes.c_int32),
+                ("root_node", ctypes.c_int32), ("alpha", ctypes.c_int64),
+                ("colorful_prob", ctypes.c_double), ("spmm_columns", ctypes.c_int64),
+                ("pairs_per_vertex", ctypes.c_int64), ("widest_table", ctypes.c_int64)]
+
+
+class NodeInfo(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("active", ctypes.c_int32), ("passive", ctypes.c_int32),
+                ("vertex", ctypes.c_int32), ("n_kept", ctypes.c_int32),
+                ("is_passive", ctypes.c_int32), ("columns", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("spmm_width", ctypes.c_int32), ("ema_rows", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_int64)]
+
+
+EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_destroy",
+           "sg2v_plan_info", "sg2v_plan_node", "sg2v_plan_pairs", "sg2v_graph_create", "sg2v_graph_destroy",
+           "sg2v_color", "sg2v_colorings_destroy", "sg2v_colorings_download", "sg2v_count",
+           "sg2v_count_batch", "sg2v_count_grad", "sg2v_debug_table", "sg2v_set_tuning",
+           "sg2v_get_tuning"]
+
+
+def lib():
+    """Load libsg2v.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -m paper_2009_11665_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                 ctypes.c_uint64)
+        L.sg2v_last_error.restype = ctypes.c_char_p
+        L.sg2v_version.restype = ctypes.c_char_p
+        L.sg2v_plan_create.argtypes = [P, i32, i32, ctypes.POINTER(P)]
+        L.sg2v_plan_destroy.argtypes = [P]
+        L.sg2v_plan_destroy.restype = None
+        L.sg2v_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+        L.sg2v_plan_node.argtypes = [P, i32, ctypes.POINTER(NodeInfo)]
+        L.sg2v_plan_pairs.argtypes = [P, i32, P]
+        L.sg2v_graph_create.argtypes = [i64, i64, P, P, P, u32, P, ctypes.POINTER(P)]
+        L.sg2v_graph_destroy.argtypes = [P]
+        L.sg2v_graph_destroy.restype = None
+        L.sg2v_color.argtypes = [P, i32, u64, i32, i32, P, ctypes.POINTER(P)]
+        L.sg2v_colorings_destroy.argtypes = [P]
+        L.sg2v_colorings_destroy.restype = None
+        L.sg2v_colorings_download.argtypes = [P, P, P]
+        L.sg2v_count.argtypes = [P, P, P, i32, P, P, P, P, P, P]
+        L.sg2v_count_batch.argtypes = [P, i32, P, u64, i32, i32, P, P, P]
+        L.sg2v_count_grad.argtypes = [P, P, P, i32, P, P, P]
+        L.sg2v_debug_table.argtypes = [P, P, P, i32, i32, i32, i32, P, P]
+        L.sg2v_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.sg2v_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if f.restype is ctypes.c_int:  # default restype: status codes
+                f.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise Sg2vError(st, where, lib().sg2v_last_error().decode())
+
+
+def _stream(stream=None):
+    """hipStream_t of `stream`, else of torch's current stream, else NULL."""
+    import torch
+    if stream is None:
+        if not torch.cuda.is_available():
+            return None
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(a.data_ptr())  # torch tensor
+
+
+def version() -> str:
+    return lib().sg2v_version().decode()
+
+
+class Plan:
+    """sg2v_plan: template partition, split tables, alpha and P."""
+
+    def __init__(self, parent: Sequence[int], k: Optional[int] = None):
+        par = np.ascontiguousarray(parent, np.int32)
+        self.parent = [int(x) for x in par]
+        self.t = len(par)
+        self.k = self.t if k is None else int(k)
+        h = ctypes.c_void_p()
+        _check(lib().sg2v_plan_create(_ptr(par), self.t, self.k, ctypes.byref(h)),
+               "sg2v_plan_create")
+        self.h = h
+
+    def info(self) -> PlanInfo:
+        i = PlanInfo()
+        _check(lib().sg2v_plan_info(self.h, ctypes.byref(i)), "sg2v_plan_info")
+        return i
+
+    def node(self, idx: int) -> NodeInfo:
+        i = NodeInfo()
+        _check(lib().sg2v_plan_node(self.h, idx, ctypes.byref(i)), "sg2v_plan_node")
+        return i
+
+    def nodes(self):
+        return [self.node(i) for i in range(self.info().n_nodes)]
+
+    def pairs(self, idx: int) -> np.ndarray:
+        """Split table of node idx: int32 [C(k,|T_s|), C(|T_s|,|T_a|), 2]."""
+        from math import comb
+        nd = self.node(idx)
+        na = self.node(nd.active).size
+        out = np.zeros((nd.columns, comb(nd.size, na), 2), np.int32)
+        _check(lib().sg2v_plan_pairs(self.h, idx, _ptr(out)), "sg2v_plan_pairs")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sg2v_plan_destroy(self.h)
+            self.h = None
+
+
+class Graph:
+    """sg2v_graph: symmetric CSR registered on the current device.
+
+    Pass numpy arrays (copied to the device) or torch device tensors
+    (borrowed: the Graph keeps references to them)."""
+
+    def __init__(self, n: int, row_ptr, col_idx, w=None, validate: bool = False, stream=None):
+        self.n = int(n)
+        flags = GRAPH_VALIDATE if validate else 0
+        self._keep = None
+        if isinstance(row_ptr, np.ndarray):
+            rp = np.ascontiguousarray(row_ptr, np.int64)
+            ci = np.ascontiguousarray(col_idx, np.int32)
+            wv = None if w is None else np.ascontiguousarray(w, np.float32)
+            nnz = int(rp[-1])
+        else:
+            import torch
+            rp = row_ptr.contiguous().to(torch.int64)
+            ci = col_idx.contiguous().to(torch.int32)
+            wv = None if w is None else w.contiguous().to(torch.float32)
+            nnz = int(ci.numel())
+            flags |= GRAPH_DEVICE_PTRS
+            self._keep = (rp, ci, wv)
+        self.nnz = nnz
+        self.weighted = w is not None
+        h = ctypes.c_void_p()
+        _check(lib().sg2v_graph_create(self.n, nnz, _ptr(rp), _ptr(ci), _ptr(wv), flags,
+                                       _stream(stream), ctypes.byref(h)), "sg2v_graph_create")
+        self.h = h
+
+    @classmethod
+    def from_csr(cls, g, validate: bool = False, weighted: Optional[bool] = None, stream=None):
+        """From any object with n, row_ptr, col_idx, w (numpy)."""
+        use_w = g.w if (weighted is None or weighted) else None
+        return cls(g.n, g.row_ptr, g.col_idx, use_w, validate=validate, stream=stream)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sg2v_graph_destroy(self.h)
+            self.h = None
+
+
+class Colorings:
+    """sg2v_colorings: n_colorings random colourings on the device."""
+
+    def __init__(self, graph: Graph, k: int, seed: int, n_colorings: int, first: int = 0,
+                 stream=None):
+        self.graph = graph
+        self.k, self.seed, self.count, self.first = int(k), int(seed), int(n_colorings), int(first)
+        h = ctypes.c_void_p()
+        _check(lib().sg2v_color(graph.h, self.k, self.seed, self.first, self.count,
+                                _stream(stream), ctypes.byref(h)), "sg2v_color")
+        self.h = h
+
+    def download(self, stream=None) -> np.ndarray:
+        out = np.empty((self.count, self.graph.n), np.uint8)
+        _check(lib().sg2v_colorings_download(self.h, _ptr(out), _stream(stream)),
+               "sg2v_colorings_download")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sg2v_colorings_destroy(self.h)
+            self.h = None
+
+
+def count(plan: Plan, graph: Graph, col: Colorings, mode="fp32s", stream=None):
+    """Colourful counts and estimates per colouring (sg2v_count).
+
+    Returns dict(colorful=float64[n], colorful_u64=uint64[n], estimate=float64[n],
+    mean_estimate=float, overflow=bool)."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    n = col.count
+    cf = np.zeros(n, np.float64)
+    cu = np.zeros(n, np.uint64)
+    est = np.zeros(n, np.float64)
+    mean = ctypes.c_double(0)
+    ovf = ctypes.c_int32(0)
+    _check(lib().sg2v_count(plan.h, graph.h, col.h, m, _stream(stream), _ptr(cf), _ptr(cu),
+                            _ptr(est), ctypes.byref(mean), ctypes.byref(ovf)), "sg2v_count")
+    return dict(colorful=cf, colorful_u64=cu, estimate=est, mean_estimate=mean.value,
+                overflow=bool(ovf.value))
+
+
+def count_batch(plans: Sequence[Plan], graph: Graph, seed: int, n_colorings: int, mode="fp32s",
+                stream=None):
+    """Several templates x n_colorings colourings (sg2v_count_batch).
+    Returns (colorful, estimate) arrays of shape [n_plans, n_colorings]."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    arr = (ctypes.c_void_p * len(plans))(*[p.h.value for p in plans])
+    cf = np.zeros((len(plans), n_colorings), np.float64)
+    est = np.zeros((len(plans), n_colorings), np.float64)
+    _check(lib().sg2v_count_batch(arr, len(plans), graph.h, seed, n_colorings, m, _stream(stream),
+                                  _ptr(cf), _ptr(est)), "sg2v_count_batch")
+    return cf, est
+
+
+def debug_table(plan: Plan, graph: Graph, col: Colorings, node: int, kind: int = 0,
+                which: int = 0, mode="fp64", stream=None) -> np.ndarray:
+    """Table of `node` (kind 0: M_s, kind 1: B = A M_s) for colouring `which`,
+    as float64 (uint64 in U64 mode), shape [n, C(k, |T_s|)]."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    ni = plan.node(node)
+    cols = plan.k if (ni.size == 1) else ni.columns
+    out = np.zeros((graph.n, cols), np.uint64 if m == U64 else np.float64)
+    _check(lib().sg2v_debug_table(plan.h, graph.h, col.h, m, which, node, kind, _ptr(out),
+                                  _stream(stream)), "sg2v_debug_table")
+    return out
+
+
+def count_grad(plan: Plan, graph: Graph, col: Colorings, grad_colorful, mode="fp64",
+               stream=None):
+    """d(sum_j grad_colorful[j] * colorful[j]) / d(A_G(i,j)) per directed CSR
+    entry, as a torch tensor on the current device (sg2v_count_grad)."""
+    import torch
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    gc = np.ascontiguousarray(grad_colorful, np.float64)
+    dt = torch.float64 if m == FP64 else torch.float32
+    out = torch.empty(graph.nnz, dtype=dt, device="cuda")
+    _check(lib().sg2v_count_grad(plan.h, graph.h, col.h, m, _ptr(gc), _ptr(out), _stream(stream)),
+           "sg2v_count_grad")
+    return out
+
+
+def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0):
+    t = Tuning(spmm_width, ema_rows, batch, 0, budget_bytes)
+    _check(lib().sg2v_set_tuning(ctypes.byref(t)), "sg2v_set_tuning")
+
+
+def get_tuning() -> Tuning:
+    t = Tuning()
+    _check(lib().sg2v_get_tuning(ctypes.byref(t)), "sg2v_get_tuning")
+    return t

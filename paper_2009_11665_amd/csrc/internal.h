@@ -1,0 +1,84 @@
+// Internal structures shared by the planner (plan.cpp) and the device
+// runtime (runtime.hip).  Not part of the public interface.
+#pragma once
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sg2v.h"
+
+namespace sg2v {
+
+void set_error(const char *fmt, ...);
+
+// binomial coefficients C(a, b) for 0 <= a, b <= 64 (exact in int64 for the
+// sizes used here: a <= SG2V_KMAX).
+int64_t binom(int a, int b);
+
+// colexicographic rank of a colour set given as a bit mask (bit c = colour c):
+// rank = sum_i C(c_i, i) over the sorted elements c_1 < ... < c_m.
+int64_t colex_rank(uint32_t mask);
+// inverse: the mask of size m with the given rank among k colours.
+uint32_t colex_unrank(int64_t rank, int m, int k);
+
+// One distinct rooted sub-template.  Nodes are stored children first.
+struct Node {
+  int size = 1;
+  int active = -1;   // node id of the active child (keeps the root)
+  int passive = -1;  // node id of the passive child (cut-off subtree)
+  int vertex = 0;    // template vertex rooting the first occurrence
+  int n_kept = 0;    // number of that vertex's first children it keeps
+  int64_t cols = 0;  // C(k, size)
+  int n_active_uses = 0;   // splits using this node as active child
+  int n_passive_uses = 0;  // splits using this node as passive child
+  std::string canon;       // rooted canonical form
+  // split tables (size > 1):
+  int np = 0;                  // pairs per output column = C(size, size_a)
+  std::vector<int32_t> pairs;  // [cols][np] x (ia, ip)
+  std::vector<int32_t> drop;   // active child is one vertex: [k][cols] -> rank(C\{c}) or -1
+};
+
+enum RootKind {
+  ROOT_SINGLE = 0,   // root split's active child is one vertex:  X = B_Q, no Y
+  ROOT_FUSED = 1,    // active child is itself a one-vertex-active split used only
+                     // here: X = B of its passive, Y = B_Q
+  ROOT_GENERAL = 2,  // X = M of the active child, Y = B_Q
+  ROOT_VERTEX = 3,   // the template is one vertex
+};
+
+struct Plan {
+  int t = 0, k = 0;
+  std::vector<int32_t> parent;
+  std::vector<Node> nodes;
+  int root = -1;
+  int64_t alpha = 1;
+  double P = 1.0;
+  // root reduction: for every colour c, L entries (x, y): the sum over the
+  // list of X(i, x) * Y(i, y) equals sum_C M_0(i, C) for a vertex of colour c.
+  int root_kind = ROOT_VERTEX;
+  int root_x_node = -1;  // node whose B (or M for ROOT_GENERAL) is X
+  int root_y_node = -1;  // node whose B is Y (-1: Y = 1)
+  int64_t root_L = 0;
+  std::vector<int32_t> root_list;  // [k][L] x (x, y)
+  // nodes whose tables are never materialised (fused into the root)
+  std::vector<char> fused;
+
+  // device copies of the tables, uploaded on first use per device
+  struct DeviceTables {
+    int device = -1;
+    std::vector<void *> pairs, drop;  // per node
+    void *root_list = nullptr;
+  };
+  mutable std::mutex mu;
+  mutable std::vector<DeviceTables> dev;
+};
+
+sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out);
+
+}  // namespace sg2v
+
+struct sg2v_plan {
+  sg2v::Plan p;
+};

@@ -1,0 +1,721 @@
+// Kernels of the colour-coding dynamic programme (SubGraph2Vec, arXiv
+// 2009.11665) for gfx950.  Host-side launchers are at the end of the file.
+#include <climits>
+#include <type_traits>
+
+#include "kernels.h"
+#include "launch.h"
+
+namespace sg2v {
+
+// ===========================================================================
+// Random colouring (Sec. 2.3.1): colour of v in colouring j is
+//   h = F(seed ^ F((j << 40) | v)),  colour = (hi32(h) * k) >> 32,
+// F = SplitMix64's output finaliser (Steele, Lea & Flood 2014).
+
+__device__ inline uint64_t fin64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_color(uint8_t *__restrict__ out, int64_t n, int32_t k, uint64_t seed,
+                        int32_t first, int32_t count) {
+  int64_t total = n * count;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = x / n, v = x - j * n;
+    uint64_t h = fin64(seed ^ fin64(((uint64_t)(first + j) << 40) | (uint64_t)v));
+    out[x] = (uint8_t)(((h >> 32) * (uint64_t)k) >> 32);
+  }
+}
+
+void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
+                  int32_t count, hipStream_t s) {
+  int64_t total = n * count;
+  int64_t blocks = (total + BLOCK - 1) / BLOCK;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  k_color<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(out, n, k, seed, first, count);
+}
+
+// ===========================================================================
+// Neighbour-colour histogram: B = A_G M_1 where M_1 is the one-hot table of a
+// single-vertex passive child (Alg. 2 sets M_s(i, colour of i) = 1), so
+//   H(i, jj*k + c) = sum_{e in row i} w_e [colour_jj(col_idx[e]) == c].
+// One wave per row, lanes over neighbours; lane c keeps colour c's sum.
+// Unweighted counts use a ballot per colour, weighted sums a fixed-order
+// butterfly, so the result does not depend on scheduling.
+
+template <typename T, bool WEIGHTED>
+__global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+  T *H = (T *)a.H;
+  for (int64_t i = wave; i < a.n; i += nwaves) {
+    const int64_t beg = a.row_ptr[i], end = a.row_ptr[i + 1];
+    for (int jj = 0; jj < a.b; ++jj) {
+      const uint8_t *col = a.colors + (int64_t)(a.j0 + jj) * a.n;
+      T acc = T(0);
+      for (int64_t base = beg; base < end; base += WAVE) {
+        int64_t e = base + lane;
+        int c = 255;
+        T wv = T(1);
+        if (e < end) {
+          c = col[a.col_idx[e]];
+          if constexpr (WEIGHTED) wv = (T)a.w[e];
+        }
+        for (int cc = 0; cc < a.k; ++cc) {
+          if constexpr (!WEIGHTED) {
+            uint64_t m = __ballot(c == cc);
+            if (lane == cc) acc += (T)__popcll(m);
+          } else {
+            T v = (c == cc) ? wv : T(0);
+            for (int off = 1; off < WAVE; off <<= 1) v += shfl_xor(v, off);
+            if (lane == cc) acc += v;
+          }
+        }
+      }
+      if (lane < a.k) H[i * a.ldh + (int64_t)jj * a.k + lane] = acc;
+    }
+  }
+}
+
+// ===========================================================================
+// Neighbour aggregation B = A_G M_p (Sec. 4.1, Alg. 4; Alg. 5 lines 7-9) as a
+// CSR SpMM over one column chunk of W = G * N columns per blockIdx.y.
+//
+// Rows are cut into tasks of at most a fixed number of neighbours (long rows
+// become several tasks that write partial rows, combined by k_spmm_combine in
+// a fixed order).  Tasks are sorted by length, longest first, and grouped in
+// units of WAVES_PER_BLOCK * rpw tasks: each wave serves rpw tasks, each task
+// 64/rpw lanes = (64/rpw)/G streams of G lanes, and each stream of G lanes
+// reads one neighbour row segment of W elements with 16-byte loads.  The
+// neighbour indices of a task are loaded once per 64/rpw neighbours and
+// broadcast with ds_bpermute.  Blocks walk units with a grid stride.
+//
+// The column maximum of B (FP32S) is reduced in registers, then across the
+// block in LDS, then one atomicMax per column per block.
+
+template <typename T, int G, bool WEIGHTED>
+__global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
+  constexpr int N = V16<T>::N;
+  constexpr int W = G * N;
+  using A = Arith<T>;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int sub = lane % G;
+  const int64_t col0 = (int64_t)blockIdx.y * W + sub * N;
+  const T *__restrict__ M = (const T *)a.M;
+  T *__restrict__ B = (T *)a.B;
+  T *__restrict__ Pt = (T *)a.partial;
+  bool ovf = false;
+  T cmax[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) cmax[u] = T(0);
+
+  for (int64_t unit = blockIdx.x; unit < a.n_units; unit += gridDim.x) {
+    const int rpw = a.unit_rpw[unit];
+    const int lpt = WAVE / rpw;        // lanes per task
+    const int tloc = lane / lpt;       // task within the wave
+    const int tl = lane - tloc * lpt;  // lane within the task
+    const int streams = lpt / G;
+    const int stream = tl / G;
+    const int gbase = tloc * lpt;      // first lane of the task's group
+    const int tidx = wv * rpw + tloc;
+    const bool valid = tidx < a.unit_ntask[unit];
+    int64_t beg = 0;
+    int len = 0, row = 0, slot = -1;
+    if (valid) {
+      const int64_t t = (int64_t)a.unit_task[unit] + tidx;
+      row = a.task_row[t];
+      beg = a.task_beg[t];
+      len = a.task_len[t];
+      slot = a.task_slot[t];
+    }
+    V16<T> acc0, acc1, acc2, acc3;
+#pragma unroll
+    for (int u = 0; u < N; ++u) acc0.x[u] = acc1.x[u] = acc2.x[u] = acc3.x[u] = T(0);
+
+    for (int base = 0; base < len; base += lpt) {
+      const int e = base + tl;
+      int my_j = 0;
+      float my_w = 1.0f;
+      if (e < len) {
+        my_j = a.col_idx[beg + e];
+        if constexpr (WEIGHTED) my_w = a.w[beg + e];
+      }
+      const int cnt = min(lpt, len - base);
+      int s = stream;
+      for (; s + 3 * streams < cnt; s += 4 * streams) {
+        const int j0 = shfl_i32(my_j, gbase + s);
+        const int j1 = shfl_i32(my_j, gbase + s + streams);
+        const int j2 = shfl_i32(my_j, gbase + s + 2 * streams);
+        const int j3 = shfl_i32(my_j, gbase + s + 3 * streams);
+        const V16<T> v0 = *(const V16<T> *)(M + (int64_t)j0 * a.ldm + col0);
+        const V16<T> v1 = *(const V16<T> *)(M + (int64_t)j1 * a.ldm + col0);
+        const V16<T> v2 = *(const V16<T> *)(M + (int64_t)j2 * a.ldm + col0);
+        const V16<T> v3 = *(const V16<T> *)(M + (int64_t)j3 * a.ldm + col0);
+        if constexpr (WEIGHTED) {
+          const T w0 = (T)shfl(my_w, gbase + s), w1 = (T)shfl(my_w, gbase + s + streams);
+          const T w2 = (T)shfl(my_w, gbase + s + 2 * streams);
+          const T w3 = (T)shfl(my_w, gbase + s + 3 * streams);
+#pragma unroll
+          for (int u = 0; u < N; ++u) {
+            acc0.x[u] = A::fma(w0, v0.x[u], acc0.x[u], ovf);
+            acc1.x[u] = A::fma(w1, v1.x[u], acc1.x[u], ovf);
+            acc2.x[u] = A::fma(w2, v2.x[u], acc2.x[u], ovf);
+            acc3.x[u] = A::fma(w3, v3.x[u], acc3.x[u], ovf);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < N; ++u) {
+            acc0.x[u] = A::add(acc0.x[u], v0.x[u], ovf);
+            acc1.x[u] = A::add(acc1.x[u], v1.x[u], ovf);
+            acc2.x[u] = A::add(acc2.x[u], v2.x[u], ovf);
+            acc3.x[u] = A::add(acc3.x[u], v3.x[u], ovf);
+          }
+        }
+      }
+      for (; s < cnt; s += streams) {
+        const int j0 = shfl_i32(my_j, gbase + s);
+        const V16<T> v0 = *(const V16<T> *)(M + (int64_t)j0 * a.ldm + col0);
+        if constexpr (WEIGHTED) {
+          const T w0 = (T)shfl(my_w, gbase + s);
+#pragma unroll
+          for (int u = 0; u < N; ++u) acc0.x[u] = A::fma(w0, v0.x[u], acc0.x[u], ovf);
+        } else {
+#pragma unroll
+          for (int u = 0; u < N; ++u) acc0.x[u] = A::add(acc0.x[u], v0.x[u], ovf);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      T x = A::add(A::add(acc0.x[u], acc1.x[u], ovf), A::add(acc2.x[u], acc3.x[u], ovf), ovf);
+      // butterfly across the task's streams (lanes differing in bits >= log2 G)
+      for (int off = G; off < lpt; off <<= 1) x = A::add(x, shfl_xor(x, off), ovf);
+      acc0.x[u] = x;
+    }
+    if (valid && stream == 0) {
+      if (slot < 0) {
+        *(V16<T> *)(B + (int64_t)row * a.ldb + col0) = acc0;
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+          if (col0 + u < a.ncols_valid && acc0.x[u] > cmax[u]) cmax[u] = acc0.x[u];
+      } else {
+        *(V16<T> *)(Pt + (int64_t)slot * a.ldb + col0) = acc0;
+      }
+    }
+  }
+  if constexpr (is_u64<T>) {
+    // U64: flags only for valid columns are meaningful; padding columns may
+    // hold arbitrary bits and are excluded by the caller zeroing padding.
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+  if (a.mx) {
+    // lanes with equal `sub` hold the same columns
+    __shared__ float red[WAVES_PER_BLOCK][WAVE];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      float x = (float)cmax[u];
+      for (int off = G; off < WAVE; off <<= 1) x = fmaxf(x, shfl_xor(x, off));
+      cmax[u] = (T)x;
+    }
+    for (int u = 0; u < N; ++u) {
+      if (lane < G) red[wv][lane] = (float)cmax[u];
+      __syncthreads();
+      if (wv == 0 && lane < G) {
+        float x = red[0][lane];
+        for (int q = 1; q < WAVES_PER_BLOCK; ++q) x = fmaxf(x, red[q][lane]);
+        const int64_t c = (int64_t)blockIdx.y * W + lane * N + u;
+        if (c < a.ncols_valid && x > 0.f) atomicMax(a.mx + c, __float_as_uint(x));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Sum the partial rows of long rows in slot order, write them to B and fold
+// them into the column maximum.  Grid: (column vectors, groups of rows).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
+  constexpr int N = V16<T>::N;
+  using A = Arith<T>;
+  const int64_t vcol = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // vector column index
+  const int64_t c0 = vcol * N;
+  if (c0 >= a.ld) return;
+  const T *P = (const T *)a.partial;
+  T *B = (T *)a.B;
+  bool ovf = false;
+  T cmax[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) cmax[u] = T(0);
+  for (int h = blockIdx.y; h < a.n_long; h += gridDim.y) {
+    const int row = a.long_row[h];
+    const int s0 = a.long_slot0[h], ns = a.long_nslot[h];
+    V16<T> acc = *(const V16<T> *)(P + (int64_t)s0 * a.ld + c0);
+    for (int s = 1; s < ns; ++s) {
+      const V16<T> v = *(const V16<T> *)(P + (int64_t)(s0 + s) * a.ld + c0);
+#pragma unroll
+      for (int u = 0; u < N; ++u) acc.x[u] = A::add(acc.x[u], v.x[u], ovf);
+    }
+    *(V16<T> *)(B + (int64_t)row * a.ld + c0) = acc;
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (acc.x[u] > cmax[u]) cmax[u] = acc.x[u];
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf && c0 < a.ncols_valid) atomicOr(a.ovf, 1);
+  }
+  if (a.mx) {
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (c0 + u < a.ncols_valid && (float)cmax[u] > 0.f)
+        atomicMax(a.mx + c0 + u, __float_as_uint((float)cmax[u]));
+  }
+}
+
+// ===========================================================================
+// Count combination, general split (Alg. 3 stage 2; Alg. 5 lines 10-13):
+//   M_s(i, C) = sum over pairs (I_a, I_p) of C of M_a(i, I_a) * B(i, I_p).
+// A block stages R rows of M_a and B (one colouring, blockIdx.y) in LDS --
+// scaled to a common exponent in FP32S mode -- then each thread owns output
+// columns C and keeps R accumulators.  Pair indices are stored
+// pair-major ([q][C]) so that a wave reads them coalesced.  Blocks walk row
+// tiles with a grid stride; the running column maximum sits in LDS.
+
+template <typename T, int R, bool SCALED, bool STAGE>
+__global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
+  using A = Arith<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int j = blockIdx.y;
+  const int sa = a.Ca | 1, sb = a.Cb | 1;  // odd row strides in LDS
+  T *la = (T *)smem;
+  T *lb = la + (STAGE ? R * sa : 0);
+  float *lmx = (float *)(lb + (STAGE ? R * sb : 0));
+  const T *Ma = (const T *)a.Ma;
+  const T *Bt = (const T *)a.B;
+  T *Ms = (T *)a.Ms;
+  const int2 *pairs = (const int2 *)a.pairs;
+  const float *fa = SCALED ? a.fa + (int64_t)j * a.Ca : nullptr;
+  const float *fb = SCALED ? a.fb + (int64_t)j * a.Cb : nullptr;
+  bool ovf = false;
+  if (SCALED)
+    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0.f;
+  const int64_t ntiles = (a.n + R - 1) / R;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * R;
+    if constexpr (STAGE) {
+      __syncthreads();
+      for (int x = threadIdx.x; x < R * a.Ca; x += BLOCK) {
+        const int r = x / a.Ca, c = x - r * a.Ca;
+        const int64_t row = r0 + r;
+        T v = T(0);
+        if (row < a.n) {
+          v = Ma[row * a.lda + (int64_t)j * a.Ca + c];
+          if constexpr (SCALED) v *= fa[c];
+        }
+        la[r * sa + c] = v;
+      }
+      for (int x = threadIdx.x; x < R * a.Cb; x += BLOCK) {
+        const int r = x / a.Cb, c = x - r * a.Cb;
+        const int64_t row = r0 + r;
+        T v = T(0);
+        if (row < a.n) {
+          v = Bt[row * a.ldb + (int64_t)j * a.Cb + c];
+          if constexpr (SCALED) v *= fb[c];
+        }
+        lb[r * sb + c] = v;
+      }
+      __syncthreads();
+    }
+    for (int C = threadIdx.x; C < a.Cs; C += BLOCK) {
+      T acc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = T(0);
+      for (int q = 0; q < a.np; ++q) {
+        const int2 p = pairs[(int64_t)q * a.Cs + C];
+        if constexpr (STAGE) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + p.x], lb[r * sb + p.y], acc[r], ovf);
+        } else {
+          T sxa = T(1), sxb = T(1);
+          if constexpr (SCALED) {
+            sxa = fa[p.x];
+            sxb = fb[p.y];
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int64_t row = r0 + r;
+            if (row < a.n) {
+              T x = Ma[row * a.lda + (int64_t)j * a.Ca + p.x];
+              T y = Bt[row * a.ldb + (int64_t)j * a.Cb + p.y];
+              if constexpr (SCALED) {
+                x *= sxa;
+                y *= sxb;
+              }
+              acc[r] = A::fma(x, y, acc[r], ovf);
+            }
+          }
+        }
+      }
+      float m = 0.f;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t row = r0 + r;
+        if (row < a.n) {
+          Ms[row * a.lds + (int64_t)j * a.Cs + C] = acc[r];
+          if constexpr (SCALED) m = fmaxf(m, (float)acc[r]);
+        }
+      }
+      if constexpr (SCALED) lmx[C] = fmaxf(lmx[C], m);
+    }
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+  if constexpr (SCALED) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
+      if (lmx[c] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + c, __float_as_uint(lmx[c]));
+      if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
+    }
+  }
+}
+
+// Count combination when the active child is one vertex (Alg. 2's
+// single-vertex table): M_s(i, C) = [col(i) in C] * B(i, C \ {col(i)}).
+// Threads own output columns; a block handles `rows_per_iter` rows at once.
+
+template <typename T, bool SCALED>
+__global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float *lmx = (float *)smem;
+  const int j = blockIdx.y;
+  const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
+  const T *Bt = (const T *)a.B;
+  T *Ms = (T *)a.Ms;
+  const float *fb = SCALED ? a.fb + (int64_t)j * a.Cb : nullptr;
+  const int cpad = (a.Cs + WAVE - 1) / WAVE * WAVE;
+  const int rpi = cpad >= BLOCK ? 1 : BLOCK / cpad;  // rows per iteration
+  const int rsub = cpad >= BLOCK ? 0 : threadIdx.x / cpad;
+  const int c0 = cpad >= BLOCK ? threadIdx.x : threadIdx.x - rsub * cpad;
+  const int cstep = cpad >= BLOCK ? BLOCK : cpad;
+  if (SCALED)
+    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0.f;
+  __syncthreads();
+  for (int64_t i0 = (int64_t)blockIdx.x * rpi; i0 < a.n; i0 += (int64_t)gridDim.x * rpi) {
+    const int64_t i = i0 + rsub;
+    if (rsub >= rpi || i >= a.n) continue;
+    const int c = col[i];
+    const T *brow = Bt + i * a.ldb + (int64_t)j * a.Cb;
+    for (int C = c0; C < a.Cs; C += cstep) {
+      const int idx = a.drop[(int64_t)c * a.Cs + C];
+      T v = T(0);
+      if (idx >= 0) {
+        v = brow[idx];
+        if constexpr (SCALED) v *= fb[idx];
+      }
+      Ms[i * a.lds + (int64_t)j * a.Cs + C] = v;
+      if constexpr (SCALED) {
+        if ((float)v > 0.f) atomicMax((unsigned *)&lmx[C], __float_as_uint((float)v));
+      }
+    }
+  }
+  if constexpr (SCALED) {
+    __syncthreads();
+    for (int cc = threadIdx.x; cc < a.Cs; cc += BLOCK) {
+      if (lmx[cc] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + cc, __float_as_uint(lmx[cc]));
+      if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + cc] = a.Eb[j];
+    }
+  }
+}
+
+// ===========================================================================
+// Root reduction (Alg. 1: sum_i sum_C M_0(i, I_C)).  For a vertex of colour c
+// the row sum of M_0 equals sum over list[c] of X(i, x) * Y(i, y), where the
+// list comes from the root split (see the planner).  One wave per row; lanes
+// stride over the list; the row value is reduced in the table type (FP32
+// mantissas in FP32S) and accumulated over rows in double (uint64 in U64).
+// Per-block partials are summed in block order by k_root_final.
+
+template <typename T, bool SCALED, bool HASY>
+__global__ void __launch_bounds__(BLOCK) k_root(RootArgs a) {
+  using A = Arith<T>;
+  using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
+  __shared__ Acc red[WAVES_PER_BLOCK];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int j = blockIdx.y;
+  const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
+  const T *X = (const T *)a.X;
+  const T *Y = (const T *)a.Y;
+  const float *fx = SCALED ? a.fx + (int64_t)j * a.Cx : nullptr;
+  const float *fy = (SCALED && HASY) ? a.fy + (int64_t)j * a.Cy : nullptr;
+  const int2 *list = (const int2 *)a.list;
+  bool ovf = false;
+  Acc tot = Acc(0);
+  const int64_t wave = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+  for (int64_t i = wave; i < a.n; i += nwaves) {
+    const int c = col[i];
+    const int2 *lc = list + (int64_t)c * a.L;
+    const T *xr = X + i * a.ldx + (int64_t)j * a.Cx;
+    const T *yr = HASY ? Y + i * a.ldy + (int64_t)j * a.Cy : nullptr;
+    T s = T(0);
+    for (int64_t q = lane; q < a.L; q += WAVE) {
+      const int2 p = lc[q];
+      T x = xr[p.x];
+      if constexpr (SCALED) x *= fx[p.x];
+      if constexpr (HASY) {
+        T y = yr[p.y];
+        if constexpr (SCALED) y *= fy[p.y];
+        s = A::fma(x, y, s, ovf);
+      } else {
+        s = A::add(s, x, ovf);
+      }
+    }
+    for (int off = 1; off < WAVE; off <<= 1) s = A::add(s, shfl_xor(s, off), ovf);
+    if constexpr (is_u64<Acc>) {
+      tot = A::add(tot, s, ovf);
+    } else {
+      tot += (double)s;
+    }
+  }
+  if (lane == 0) red[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Acc b = red[0];
+    for (int q = 1; q < WAVES_PER_BLOCK; ++q) {
+      if constexpr (is_u64<Acc>) b = A::add(b, red[q], ovf);
+      else b += red[q];
+    }
+    ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = b;
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+}
+
+template <typename Acc>
+__global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= b) return;
+  Acc s = partial[(int64_t)j * nblk];
+  bool o = false;
+  for (int q = 1; q < nblk; ++q) {
+    if constexpr (std::is_same<Acc, double>::value) {
+      s += partial[(int64_t)j * nblk + q];
+    } else {
+      s = Arith<uint64_t>::add(s, partial[(int64_t)j * nblk + q], o);
+    }
+  }
+  out[j] = s;
+  if (o) atomicOr(ovf, 1);
+}
+
+// ===========================================================================
+// FP32S bookkeeping.  For every colouring j of a table X with per-column
+// exponents e and column maxima mx (float bits):
+//   E[j] = max_c (e[c] + floor(log2 mx[c])) + 1   over columns with mx > 0
+//   f[c] = 2^(e[c] - E[j])                          (exact power of two)
+// so that consumers read X(i, c) * f[c] <= 1 in the common frame 2^E[j].
+
+__global__ void k_norm_prep(const int *e, const unsigned *mx, int C, float *f, int *E) {
+  const int j = blockIdx.x;
+  __shared__ int red[BLOCK];
+  int best = INT_MIN;
+  for (int c = threadIdx.x; c < C; c += BLOCK) {
+    const unsigned m = mx[(int64_t)j * C + c];
+    if (m != 0u) best = max(best, e[(int64_t)j * C + c] + ilog2_bits(m));
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const int Ej = red[0] == INT_MIN ? 0 : red[0] + 1;
+  for (int c = threadIdx.x; c < C; c += BLOCK) {
+    const unsigned m = mx[(int64_t)j * C + c];
+    f[(int64_t)j * C + c] = m ? exp2_int(e[(int64_t)j * C + c] - Ej) : 0.f;
+  }
+  if (threadIdx.x == 0) E[j] = Ej;
+}
+
+__global__ void k_root_exp(const int *EX, const int *EY, int *out, int b) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < b) out[j] = EX[j] + (EY ? EY[j] : 0);
+}
+
+__global__ void k_fill_u32(unsigned *p, int64_t n, unsigned v) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+       x += (int64_t)gridDim.x * blockDim.x)
+    p[x] = v;
+}
+
+__global__ void k_copy_i32(const int *src, int *dst, int64_t n) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+       x += (int64_t)gridDim.x * blockDim.x)
+    dst[x] = src[x];
+}
+
+// zero the padding columns [c_from, ld) of a row-major table
+template <typename T>
+__global__ void k_zero_pad(T *X, int64_t n, int64_t ld, int64_t c_from) {
+  const int64_t w = ld - c_from;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n * w;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = x / w, c = c_from + (x - i * w);
+    X[i * ld + c] = T(0);
+  }
+}
+
+// ===========================================================================
+// launchers
+
+static inline unsigned grid_cap(int64_t want, int64_t cap) {
+  if (want < 1) want = 1;
+  return (unsigned)(want < cap ? want : cap);
+}
+
+template <typename T>
+static void hist_dispatch(const HistArgs &a, int blocks, hipStream_t s) {
+  if (a.w) k_hist<T, true><<<blocks, BLOCK, 0, s>>>(a);
+  else k_hist<T, false><<<blocks, BLOCK, 0, s>>>(a);
+}
+
+void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s) {
+  if (dtype == DT_F32) hist_dispatch<float>(a, blocks, s);
+  else if (dtype == DT_F64) hist_dispatch<double>(a, blocks, s);
+  else hist_dispatch<uint64_t>(a, blocks, s);
+}
+
+template <typename T, int G>
+static void spmm_g(const SpmmArgs &a, dim3 grid, hipStream_t s) {
+  if (a.w) k_spmm<T, G, true><<<grid, BLOCK, 0, s>>>(a);
+  else k_spmm<T, G, false><<<grid, BLOCK, 0, s>>>(a);
+}
+
+template <typename T>
+static int spmm_t(const SpmmArgs &a, int G, dim3 grid, hipStream_t s) {
+  switch (G) {
+    case 2: spmm_g<T, 2>(a, grid, s); return 0;
+    case 4: spmm_g<T, 4>(a, grid, s); return 0;
+    case 8: spmm_g<T, 8>(a, grid, s); return 0;
+    case 16: spmm_g<T, 16>(a, grid, s); return 0;
+    default: return -1;
+  }
+}
+
+int launch_spmm(int dtype, const SpmmArgs &a, int G, dim3 grid, hipStream_t s) {
+  if (dtype == DT_F32) return spmm_t<float>(a, G, grid, s);
+  if (dtype == DT_F64) return spmm_t<double>(a, G, grid, s);
+  return spmm_t<uint64_t>(a, G, grid, s);
+}
+
+void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s) {
+  const int N = (dtype == DT_F32) ? 4 : 2;
+  const int64_t nvec = (a.ld + N - 1) / N;
+  dim3 grid(grid_cap((nvec + BLOCK - 1) / BLOCK, 1 << 20), grid_cap((a.n_long + 31) / 32, 4096));
+  if (a.n_long == 0) return;
+  if (dtype == DT_F32) k_spmm_combine<float><<<grid, BLOCK, 0, s>>>(a);
+  else if (dtype == DT_F64) k_spmm_combine<double><<<grid, BLOCK, 0, s>>>(a);
+  else k_spmm_combine<uint64_t><<<grid, BLOCK, 0, s>>>(a);
+}
+
+template <typename T, int R, bool SC, bool ST>
+static void ema_g_launch(const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+  auto kern = k_ema_general<T, R, SC, ST>;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kern<<<grid, BLOCK, lds, s>>>(a);
+}
+
+template <typename T, bool SC, bool ST>
+static int ema_g_r(const EmaArgs &a, int R, dim3 grid, size_t lds, hipStream_t s) {
+  switch (R) {
+    case 1: ema_g_launch<T, 1, SC, ST>(a, grid, lds, s); return 0;
+    case 2: ema_g_launch<T, 2, SC, ST>(a, grid, lds, s); return 0;
+    case 4: ema_g_launch<T, 4, SC, ST>(a, grid, lds, s); return 0;
+    case 8: ema_g_launch<T, 8, SC, ST>(a, grid, lds, s); return 0;
+    case 16: ema_g_launch<T, 16, SC, ST>(a, grid, lds, s); return 0;
+    default: return -1;
+  }
+}
+
+int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
+                       hipStream_t s) {
+  if (dtype == DT_F32)
+    return stage ? ema_g_r<float, true, true>(a, R, grid, lds, s)
+                 : ema_g_r<float, true, false>(a, R, grid, lds, s);
+  if (dtype == DT_F64)
+    return stage ? ema_g_r<double, false, true>(a, R, grid, lds, s)
+                 : ema_g_r<double, false, false>(a, R, grid, lds, s);
+  return stage ? ema_g_r<uint64_t, false, true>(a, R, grid, lds, s)
+               : ema_g_r<uint64_t, false, false>(a, R, grid, lds, s);
+}
+
+void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+  if (dtype == DT_F32) {
+    auto kern = k_ema_single<float, true>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    kern<<<grid, BLOCK, lds, s>>>(a);
+  } else if (dtype == DT_F64) {
+    k_ema_single<double, false><<<grid, BLOCK, 0, s>>>(a);
+  } else {
+    k_ema_single<uint64_t, false><<<grid, BLOCK, 0, s>>>(a);
+  }
+}
+
+void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) {
+  const bool hy = a.Y != nullptr;
+  if (dtype == DT_F32) {
+    if (hy) k_root<float, true, true><<<grid, BLOCK, 0, s>>>(a);
+    else k_root<float, true, false><<<grid, BLOCK, 0, s>>>(a);
+  } else if (dtype == DT_F64) {
+    if (hy) k_root<double, false, true><<<grid, BLOCK, 0, s>>>(a);
+    else k_root<double, false, false><<<grid, BLOCK, 0, s>>>(a);
+  } else {
+    if (hy) k_root<uint64_t, false, true><<<grid, BLOCK, 0, s>>>(a);
+    else k_root<uint64_t, false, false><<<grid, BLOCK, 0, s>>>(a);
+  }
+}
+
+void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
+                       hipStream_t s) {
+  if (dtype == DT_U64)
+    k_root_final<uint64_t><<<1, 64, 0, s>>>((const uint64_t *)partial, nblk, b, (uint64_t *)out, ovf);
+  else
+    k_root_final<double><<<1, 64, 0, s>>>((const double *)partial, nblk, b, (double *)out, ovf);
+}
+
+void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,
+                      hipStream_t s) {
+  k_norm_prep<<<b, BLOCK, 0, s>>>(e, mx, C, f, E);
+}
+
+void launch_root_exp(const int *EX, const int *EY, int *out, int b, hipStream_t s) {
+  k_root_exp<<<(b + 63) / 64, 64, 0, s>>>(EX, EY, out, b);
+}
+
+void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill_u32<<<grid_cap((n + BLOCK - 1) / BLOCK, 4096), BLOCK, 0, s>>>(p, n, v);
+}
+
+void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_copy_i32<<<grid_cap((n + BLOCK - 1) / BLOCK, 4096), BLOCK, 0, s>>>(src, dst, n);
+}
+
+void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, hipStream_t s) {
+  if (c_from >= ld || n == 0) return;
+  const unsigned g = grid_cap((n * (ld - c_from) + BLOCK - 1) / BLOCK, 65536);
+  if (dtype == DT_F32) k_zero_pad<float><<<g, BLOCK, 0, s>>>((float *)X, n, ld, c_from);
+  else if (dtype == DT_F64) k_zero_pad<double><<<g, BLOCK, 0, s>>>((double *)X, n, ld, c_from);
+  else k_zero_pad<uint64_t><<<g, BLOCK, 0, s>>>((uint64_t *)X, n, ld, c_from);
+}
+
+}  // namespace sg2v

@@ -1,0 +1,114 @@
+// Kernel argument blocks and launchers (host side of kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg2v {
+
+enum DType { DT_F64 = 0, DT_F32 = 1, DT_U64 = 2 };
+
+struct HistArgs {
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const float *w;        // nullable
+  const uint8_t *colors; // colouring-major
+  int64_t n;
+  int32_t k;
+  int32_t j0;            // first colouring of the pass
+  int32_t b;             // colourings in the pass
+  void *H;               // n x ldh
+  int64_t ldh;
+};
+
+struct SpmmArgs {
+  const int32_t *col_idx;
+  const float *w;          // nullable
+  const int32_t *task_row;
+  const int64_t *task_beg;
+  const int32_t *task_len;
+  const int32_t *task_slot;  // -1: write B; else partial row index
+  const int32_t *unit_task;  // first task of each unit
+  const int8_t *unit_rpw;    // tasks per wave in the unit
+  const int16_t *unit_ntask; // tasks in the unit
+  int64_t n_units;
+  const void *M;
+  int64_t ldm;
+  void *B;
+  int64_t ldb;
+  void *partial;           // n_slots x ldb
+  int64_t ncols_valid;
+  unsigned *mx;            // FP32S column maxima (nullable)
+  int *ovf;
+};
+
+struct CombineArgs {
+  const void *partial;
+  void *B;
+  int64_t ld;
+  int64_t ncols_valid;
+  const int32_t *long_row;
+  const int32_t *long_slot0;
+  const int32_t *long_nslot;
+  int32_t n_long;
+  unsigned *mx;
+  int *ovf;
+};
+
+struct EmaArgs {
+  const void *Ma;
+  int64_t lda;
+  const void *B;
+  int64_t ldb;
+  void *Ms;
+  int64_t lds;
+  const int32_t *pairs;  // int2 [np][Cs]
+  const int32_t *drop;   // [k][Cs] (one-vertex active child)
+  int32_t np, Cs, Ca, Cb;
+  int64_t n;
+  const uint8_t *colors;
+  int32_t j0;
+  const float *fa, *fb;  // FP32S column factors of M_a and B (per colouring block)
+  const int *Ea, *Eb;    // FP32S frame exponents per colouring
+  unsigned *mx;          // FP32S output column maxima
+  int *es;               // FP32S output column exponents
+  int *ovf;
+};
+
+struct RootArgs {
+  const void *X;
+  int64_t ldx;
+  int32_t Cx;
+  const void *Y;  // nullable (Y = 1)
+  int64_t ldy;
+  int32_t Cy;
+  const int32_t *list;  // int2 [k][L]
+  int64_t L;
+  int64_t n;
+  const uint8_t *colors;
+  int32_t j0;
+  const float *fx, *fy;
+  void *partial;  // [b][gridDim.x] double or uint64
+  int *ovf;
+};
+
+void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
+                  int32_t count, hipStream_t s);
+void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s);
+int launch_spmm(int dtype, const SpmmArgs &a, int G, dim3 grid, hipStream_t s);
+void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s);
+int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
+                       hipStream_t s);
+void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s);
+void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
+void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
+                       hipStream_t s);
+void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,
+                      hipStream_t s);
+// FP32S: frame exponent of the root value, E_X + E_Y per colouring
+void launch_root_exp(const int *EX, const int *EY, int *out, int b, hipStream_t s);
+void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
+void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s);
+void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, hipStream_t s);
+
+}  // namespace sg2v

@@ -1,0 +1,411 @@
+// Template planner: partition of a tree template into active/passive
+// sub-templates (Sec. 2.3.2), deduplication of isomorphic rooted
+// sub-templates, colour-set column indices (Table 1) and the split index
+// tables consumed by the multiply-add (Alg. 3 stage 2, Alg. 5), the
+// automorphism count alpha and the colourful probability P (Alg. 1).
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <new>
+
+#include "internal.h"
+
+namespace sg2v {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+const char *last_error() { return g_err; }
+
+int64_t binom(int a, int b) {
+  static int64_t tab[65][65];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int x = 0; x <= 64; ++x) {
+      tab[x][0] = 1;
+      for (int y = 1; y <= 64; ++y) tab[x][y] = (x == 0) ? 0 : tab[x - 1][y - 1] + tab[x - 1][y];
+    }
+  });
+  if (a < 0 || b < 0 || a > 64 || b > 64) return 0;
+  return tab[a][b];
+}
+
+int64_t colex_rank(uint32_t mask) {
+  int64_t r = 0;
+  int i = 0;
+  for (int c = 0; c < 32; ++c)
+    if (mask >> c & 1u) r += binom(c, ++i);
+  return r;
+}
+
+uint32_t colex_unrank(int64_t rank, int m, int k) {
+  // greedy from the largest element: c_m is the largest c with C(c, m) <= rank
+  uint32_t mask = 0;
+  int hi = k - 1;
+  for (int i = m; i >= 1; --i) {
+    int c = hi;
+    while (binom(c, i) > rank) --c;
+    mask |= 1u << c;
+    rank -= binom(c, i);
+    hi = c - 1;
+  }
+  return mask;
+}
+
+namespace {
+
+struct Tree {
+  int t = 0, root = -1;
+  std::vector<std::vector<int>> ch;  // children in increasing vertex order
+  std::vector<std::string> full_canon;
+};
+
+sg2v_status tree_from_parent(const int32_t *parent, int t, Tree &T) {
+  T.t = t;
+  T.ch.assign(t, {});
+  int roots = 0;
+  for (int v = 0; v < t; ++v) {
+    if (parent[v] == -1) {
+      T.root = v;
+      ++roots;
+    } else if (parent[v] < 0 || parent[v] >= t || parent[v] == v) {
+      set_error("sg2v_plan_create: parent[%d] = %d out of range", v, parent[v]);
+      return SG2V_ENOTTREE;
+    }
+  }
+  if (roots != 1) {
+    set_error("sg2v_plan_create: %d roots (exactly one parent entry must be -1)", roots);
+    return SG2V_ENOTTREE;
+  }
+  // every vertex must reach the root (no cycles)
+  for (int v = 0; v < t; ++v) {
+    int u = v, steps = 0;
+    while (u != T.root && steps++ <= t) u = parent[u];
+    if (u != T.root) {
+      set_error("sg2v_plan_create: vertex %d does not reach the root (cycle)", v);
+      return SG2V_ENOTTREE;
+    }
+  }
+  for (int v = 0; v < t; ++v)
+    if (v != T.root) T.ch[parent[v]].push_back(v);
+  // AHU canonical strings of full subtrees, leaves first
+  T.full_canon.assign(t, "");
+  std::function<const std::string &(int)> canon = [&](int v) -> const std::string & {
+    std::vector<std::string> kids;
+    for (int c : T.ch[v]) kids.push_back(canon(c));
+    std::sort(kids.begin(), kids.end());
+    std::string s = "(";
+    for (auto &x : kids) s += x;
+    s += ")";
+    T.full_canon[v] = s;
+    return T.full_canon[v];
+  };
+  canon(T.root);
+  return SG2V_OK;
+}
+
+std::string kept_canon(const Tree &T, int v, int n_kept) {
+  std::vector<std::string> kids;
+  for (int i = 0; i < n_kept; ++i) kids.push_back(T.full_canon[T.ch[v][i]]);
+  std::sort(kids.begin(), kids.end());
+  std::string s = "(";
+  for (auto &x : kids) s += x;
+  return s + ")";
+}
+
+// |Aut| of a rooted tree: product over vertices of the automorphisms of the
+// children and the factorials of the multiplicities of identical children.
+int64_t rooted_aut(const std::vector<std::vector<int>> &adj, int v, int from,
+                   std::vector<std::string> &canon) {
+  int64_t a = 1;
+  std::vector<std::string> kids;
+  for (int u : adj[v]) {
+    if (u == from) continue;
+    a *= rooted_aut(adj, u, v, canon);
+    kids.push_back(canon[u]);
+  }
+  std::sort(kids.begin(), kids.end());
+  for (size_t i = 0; i < kids.size();) {
+    size_t j = i;
+    while (j < kids.size() && kids[j] == kids[i]) ++j;
+    for (size_t f = 2; f <= j - i; ++f) a *= (int64_t)f;
+    i = j;
+  }
+  std::string s = "(";
+  for (auto &x : kids) s += x;
+  canon[v] = s + ")";
+  return a;
+}
+
+// |Aut(T)| of the unrooted tree: root at its centre; with two centres, also
+// count the swap of the two halves when they are isomorphic.
+int64_t tree_automorphisms(const int32_t *parent, int t) {
+  if (t <= 1) return 1;
+  std::vector<std::vector<int>> adj(t);
+  for (int v = 0; v < t; ++v)
+    if (parent[v] >= 0) {
+      adj[v].push_back(parent[v]);
+      adj[parent[v]].push_back(v);
+    }
+  std::vector<int> deg(t);
+  std::vector<int> layer;
+  for (int v = 0; v < t; ++v) {
+    deg[v] = (int)adj[v].size();
+    if (deg[v] <= 1) layer.push_back(v);
+  }
+  int remaining = t;
+  while (remaining > 2) {
+    std::vector<int> next;
+    for (int v : layer) {
+      --remaining;
+      for (int u : adj[v])
+        if (--deg[u] == 1) next.push_back(u);
+    }
+    layer = next;
+  }
+  std::vector<std::string> canon(t);
+  if (remaining == 1 || layer.size() == 1) return rooted_aut(adj, layer[0], -1, canon);
+  int c1 = layer[0], c2 = layer[1];
+  int64_t a = rooted_aut(adj, c1, c2, canon) * rooted_aut(adj, c2, c1, canon);
+  if (canon[c1] == canon[c2]) a *= 2;
+  return a;
+}
+
+}  // namespace
+
+sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
+  if (!parent) {
+    set_error("sg2v_plan_create: parent is NULL");
+    return SG2V_EINVAL;
+  }
+  if (t < 1 || k < t || k > SG2V_KMAX) {
+    set_error("sg2v_plan_create: need 1 <= t <= k <= %d (t=%d, k=%d)", SG2V_KMAX, t, k);
+    return SG2V_ERANGE;
+  }
+  Tree T;
+  sg2v_status st = tree_from_parent(parent, t, T);
+  if (st != SG2V_OK) return st;
+  Plan *P = &out;
+  P->t = t;
+  P->k = k;
+  P->parent.assign(parent, parent + t);
+
+  // Partition: node (v, n_kept) = v with its first n_kept children's subtrees.
+  // Cut the edge to the last kept child: active = (v, n_kept - 1), passive =
+  // (child, all its children).  Nodes are emitted after their children.
+  std::map<std::string, int> by_canon;
+  std::function<int(int, int)> build = [&](int v, int n_kept) -> int {
+    std::string key = kept_canon(T, v, n_kept);
+    auto it = by_canon.find(key);
+    if (it != by_canon.end()) return it->second;
+    Node nd;
+    nd.vertex = v;
+    nd.n_kept = n_kept;
+    nd.canon = key;
+    if (n_kept > 0) {
+      int tau = T.ch[v][n_kept - 1];
+      nd.active = build(v, n_kept - 1);
+      nd.passive = build(tau, (int)T.ch[tau].size());
+      nd.size = P->nodes[nd.active].size + P->nodes[nd.passive].size;
+    }
+    nd.cols = binom(k, nd.size);
+    P->nodes.push_back(nd);
+    int id = (int)P->nodes.size() - 1;
+    by_canon[key] = id;
+    return id;
+  };
+  P->root = build(T.root, (int)T.ch[T.root].size());
+  for (auto &nd : P->nodes) {
+    if (nd.active >= 0) P->nodes[nd.active].n_active_uses++;
+    if (nd.passive >= 0) P->nodes[nd.passive].n_passive_uses++;
+  }
+
+  // Split tables: for each output set C (colex order), every subset S of C
+  // with |S| = |T_a| taken in lexicographic order of positions within C.
+  for (auto &nd : P->nodes) {
+    if (nd.size == 1) continue;
+    const Node &A = P->nodes[nd.active];
+    const int m = nd.size, ma = A.size;
+    nd.np = (int)binom(m, ma);
+    nd.pairs.resize((size_t)nd.cols * nd.np * 2);
+    std::vector<int> elem(m), pos(ma);
+    for (int64_t r = 0; r < nd.cols; ++r) {
+      uint32_t C = colex_unrank(r, m, k);
+      for (int c = 0, i = 0; c < k; ++c)
+        if (C >> c & 1u) elem[i++] = c;
+      for (int i = 0; i < ma; ++i) pos[i] = i;
+      for (int q = 0; q < nd.np; ++q) {
+        uint32_t S = 0;
+        for (int i = 0; i < ma; ++i) S |= 1u << elem[pos[i]];
+        nd.pairs[((size_t)r * nd.np + q) * 2 + 0] = (int32_t)colex_rank(S);
+        nd.pairs[((size_t)r * nd.np + q) * 2 + 1] = (int32_t)colex_rank(C & ~S);
+        // next combination of positions
+        int i = ma - 1;
+        while (i >= 0 && pos[i] == m - ma + i) --i;
+        if (i < 0) break;
+        ++pos[i];
+        for (int j = i + 1; j < ma; ++j) pos[j] = pos[j - 1] + 1;
+      }
+    }
+    if (ma == 1) {
+      nd.drop.assign((size_t)k * nd.cols, -1);
+      for (int64_t r = 0; r < nd.cols; ++r) {
+        uint32_t C = colex_unrank(r, m, k);
+        for (int c = 0; c < k; ++c)
+          if (C >> c & 1u) nd.drop[(size_t)c * nd.cols + r] = (int32_t)colex_rank(C & ~(1u << c));
+      }
+    }
+  }
+
+  // Root reduction lists.
+  P->fused.assign(P->nodes.size(), 0);
+  const Node &R = P->nodes[P->root];
+  if (R.size == 1) {
+    P->root_kind = ROOT_VERTEX;
+  } else {
+    const Node &A = P->nodes[R.active];
+    P->root_y_node = R.passive;
+    std::vector<std::vector<int32_t>> lists(k);
+    int64_t nout = binom(k, t);
+    if (A.size == 1) {
+      P->root_kind = ROOT_SINGLE;
+      P->root_x_node = R.passive;
+      P->root_y_node = -1;
+      for (int64_t r = 0; r < nout; ++r) {
+        uint32_t C = colex_unrank(r, t, k);
+        for (int c = 0; c < k; ++c)
+          if (C >> c & 1u) {
+            lists[c].push_back((int32_t)colex_rank(C & ~(1u << c)));
+            lists[c].push_back(-1);
+          }
+      }
+    } else {
+      bool fuse = P->nodes[A.active].size == 1 && A.n_active_uses == 1 && A.n_passive_uses == 0;
+      P->root_kind = fuse ? ROOT_FUSED : ROOT_GENERAL;
+      P->root_x_node = fuse ? A.passive : R.active;
+      if (fuse) P->fused[R.active] = 1;
+      for (int64_t r = 0; r < nout; ++r) {
+        for (int q = 0; q < R.np; ++q) {
+          int32_t ia = R.pairs[((size_t)r * R.np + q) * 2 + 0];
+          int32_t ip = R.pairs[((size_t)r * R.np + q) * 2 + 1];
+          uint32_t S = colex_unrank(ia, A.size, k);
+          for (int c = 0; c < k; ++c)
+            if (S >> c & 1u) {
+              lists[c].push_back(fuse ? (int32_t)colex_rank(S & ~(1u << c)) : ia);
+              lists[c].push_back(ip);
+            }
+        }
+      }
+    }
+    P->root_L = (int64_t)lists[0].size() / 2;
+    P->root_list.resize((size_t)k * P->root_L * 2);
+    for (int c = 0; c < k; ++c) {
+      if ((int64_t)lists[c].size() != 2 * P->root_L) {
+        set_error("sg2v_plan_create: internal error (root list sizes differ)");
+        return SG2V_EINVAL;
+      }
+      std::copy(lists[c].begin(), lists[c].end(), P->root_list.begin() + (size_t)c * P->root_L * 2);
+    }
+  }
+  P->alpha = tree_automorphisms(parent, t);
+  double p = 1.0;
+  for (int i = 0; i < t; ++i) p *= (double)(k - i) / (double)k;
+  P->P = p;
+  return SG2V_OK;
+}
+
+}  // namespace sg2v
+
+using namespace sg2v;
+
+extern "C" {
+
+const char *sg2v_last_error(void) { return sg2v::last_error(); }
+
+const char *sg2v_version(void) { return "sg2v 0.1 (gfx950)"; }
+
+sg2v_status sg2v_plan_create(const int32_t *parent, int32_t t, int32_t k, sg2v_plan **out) {
+  if (!out) {
+    set_error("sg2v_plan_create: out is NULL");
+    return SG2V_EINVAL;
+  }
+  *out = nullptr;
+  try {
+    sg2v_plan *h = new sg2v_plan;
+    sg2v_status st = plan_build(parent, t, k, h->p);
+    if (st != SG2V_OK) {
+      delete h;
+      return st;
+    }
+    *out = h;
+    return SG2V_OK;
+  } catch (const std::bad_alloc &) {
+    set_error("sg2v_plan_create: out of host memory");
+    return SG2V_ENOMEM;
+  }
+}
+
+sg2v_status sg2v_plan_info(const sg2v_plan *plan, sg2v_plan_info_t *out) {
+  if (!plan || !out) {
+    set_error("sg2v_plan_info: null argument");
+    return SG2V_EINVAL;
+  }
+  const Plan &P = plan->p;
+  memset(out, 0, sizeof(*out));
+  out->t = P.t;
+  out->k = P.k;
+  out->n_nodes = (int32_t)P.nodes.size();
+  out->root_node = P.root;
+  out->alpha = P.alpha;
+  out->colorful_prob = P.P;
+  for (auto &nd : P.nodes) {
+    if (nd.size > 1) {
+      out->n_splits++;
+      out->pairs_per_vertex += nd.cols * nd.np;
+    }
+    if (nd.n_passive_uses > 0) {
+      out->n_passive++;
+      out->spmm_columns += nd.cols;
+    }
+    out->widest_table = std::max(out->widest_table, nd.cols);
+  }
+  return SG2V_OK;
+}
+
+sg2v_status sg2v_plan_node(const sg2v_plan *plan, int32_t node, sg2v_node_info_t *out) {
+  if (!plan || !out || node < 0 || node >= (int32_t)plan->p.nodes.size()) {
+    set_error("sg2v_plan_node: bad argument");
+    return SG2V_EINVAL;
+  }
+  const Node &nd = plan->p.nodes[node];
+  out->size = nd.size;
+  out->active = nd.active;
+  out->passive = nd.passive;
+  out->vertex = nd.vertex;
+  out->n_kept = nd.n_kept;
+  out->is_passive = nd.n_passive_uses > 0;
+  out->columns = nd.cols;
+  return SG2V_OK;
+}
+
+sg2v_status sg2v_plan_pairs(const sg2v_plan *plan, int32_t node, int32_t *out) {
+  if (!plan || !out || node < 0 || node >= (int32_t)plan->p.nodes.size() ||
+      plan->p.nodes[node].size < 2) {
+    set_error("sg2v_plan_pairs: bad argument");
+    return SG2V_EINVAL;
+  }
+  const Node &nd = plan->p.nodes[node];
+  std::copy(nd.pairs.begin(), nd.pairs.end(), out);
+  return SG2V_OK;
+}
+
+}  // extern "C"

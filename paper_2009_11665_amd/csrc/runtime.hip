@@ -1,0 +1,1125 @@
+// Host runtime of libsg2v: graph registration with degree-sorted row tasks,
+// colourings, the per-pass step schedule of the dynamic programme (Alg. 5:
+// neighbour aggregation then multiply-add per split, root reduction last),
+// a liveness-packed device workspace, FP32 per-column exponent bookkeeping,
+// and the C ABI entry points declared in include/sg2v.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+#include "launch.h"
+
+using namespace sg2v;
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, __LINE__); \
+      return SG2V_EDEVICE;                                                              \
+    }                                                                                   \
+  } while (0)
+
+#define ST_TRY(expr)               \
+  do {                             \
+    sg2v_status _s = (expr);       \
+    if (_s != SG2V_OK) return _s;  \
+  } while (0)
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// tuning
+
+sg2v_tuning_t g_tune = {0, 0, 0, 0, 0};
+std::mutex g_tune_mu;
+
+sg2v_tuning_t tuning() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune;
+}
+
+constexpr int64_t kSegment = 4096;  // neighbours per SpMM task (longer rows are split)
+constexpr int kPersistBlocks = 2048;
+
+int dtype_of(sg2v_mode m) { return m == SG2V_FP32S ? DT_F32 : (m == SG2V_FP64 ? DT_F64 : DT_U64); }
+int esize_of(int dt) { return dt == DT_F32 ? 4 : 8; }
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  sg2v_status ensure(size_t want) {
+    if (want <= bytes) return SG2V_OK;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+      return SG2V_ENOMEM;
+    }
+    bytes = want;
+    return SG2V_OK;
+  }
+};
+
+template <typename T>
+sg2v_status upload(const std::vector<T> &h, void **d, hipStream_t s) {
+  *d = nullptr;
+  if (h.empty()) return SG2V_OK;
+  HIP_TRY(hipMalloc(d, h.size() * sizeof(T)));
+  HIP_TRY(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return SG2V_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// graph
+
+struct UnitTable {
+  int32_t *unit_task = nullptr;
+  int8_t *unit_rpw = nullptr;
+  int16_t *unit_ntask = nullptr;
+  int64_t n_units = 0;
+};
+
+struct sg2v_graph {
+  int device = 0;
+  int64_t n = 0, nnz = 0;
+  int64_t *row_ptr = nullptr;
+  int32_t *col_idx = nullptr;
+  float *w = nullptr;
+  bool owns = true;
+  double max_wdeg = 0.0;  // max over rows of sum_e |w_e|
+  // SpMM tasks, sorted by length (longest first)
+  int32_t *task_row = nullptr, *task_len = nullptr, *task_slot = nullptr;
+  int64_t *task_beg = nullptr;
+  int64_t n_tasks = 0, n_slots = 0;
+  std::vector<int32_t> h_task_len;  // sorted lengths
+  int32_t *long_row = nullptr, *long_slot0 = nullptr, *long_nslot = nullptr;
+  int32_t n_long = 0;
+  std::map<int, UnitTable> units;  // by G (lanes per neighbour row segment)
+  std::vector<void *> allocs;
+  ~sg2v_graph() {
+    for (void *p : allocs) (void)hipFree(p);
+    for (auto &kv : units) {
+      (void)hipFree(kv.second.unit_task);
+      (void)hipFree(kv.second.unit_rpw);
+      (void)hipFree(kv.second.unit_ntask);
+    }
+  }
+};
+
+struct sg2v_colorings {
+  int device = 0;
+  int64_t n = 0;
+  int32_t k = 0, count = 0, first = 0;
+  uint64_t seed = 0;
+  uint8_t *d = nullptr;
+  ~sg2v_colorings() {
+    if (d) (void)hipFree(d);
+  }
+};
+
+namespace {
+
+// rows per wave for a task of `len` neighbours when a neighbour row segment
+// takes G lanes: enough streams for the task, at most 64/G tasks per wave.
+int rpw_for(int64_t len, int G) {
+  int maxr = 64 / G;
+  int r = 1;
+  while (r < maxr && (64 / (2 * r)) / G >= std::max<int64_t>(len, 1)) r *= 2;
+  return r;
+}
+
+sg2v_status build_units(sg2v_graph *g, int G, hipStream_t s, UnitTable **out) {
+  auto it = g->units.find(G);
+  if (it != g->units.end()) {
+    *out = &it->second;
+    return SG2V_OK;
+  }
+  std::vector<int32_t> ut;
+  std::vector<int8_t> ur;
+  std::vector<int16_t> un;
+  int64_t t = 0;
+  while (t < g->n_tasks) {
+    int r = rpw_for(g->h_task_len[t], G);
+    int64_t cap = (int64_t)4 * r, cnt = 0;
+    ut.push_back((int32_t)t);
+    while (t < g->n_tasks && cnt < cap && rpw_for(g->h_task_len[t], G) == r) {
+      ++t;
+      ++cnt;
+    }
+    ur.push_back((int8_t)r);
+    un.push_back((int16_t)cnt);
+  }
+  UnitTable U;
+  U.n_units = (int64_t)ut.size();
+  ST_TRY(upload(ut, (void **)&U.unit_task, s));
+  ST_TRY(upload(ur, (void **)&U.unit_rpw, s));
+  ST_TRY(upload(un, (void **)&U.unit_ntask, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  g->units[G] = U;
+  *out = &g->units[G];
+  return SG2V_OK;
+}
+
+sg2v_status graph_tasks(sg2v_graph *g, const std::vector<int64_t> &rp, hipStream_t s) {
+  const int64_t n = g->n;
+  std::vector<int32_t> row, len, slot;
+  std::vector<int64_t> beg;
+  std::vector<int32_t> lrow, lslot0, lnslot;
+  row.reserve(n);
+  int64_t slots = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t d = rp[i + 1] - rp[i];
+    if (d <= kSegment) {
+      row.push_back((int32_t)i);
+      beg.push_back(rp[i]);
+      len.push_back((int32_t)d);
+      slot.push_back(-1);
+    } else {
+      const int64_t ns = (d + kSegment - 1) / kSegment;
+      lrow.push_back((int32_t)i);
+      lslot0.push_back((int32_t)slots);
+      lnslot.push_back((int32_t)ns);
+      for (int64_t q = 0; q < ns; ++q) {
+        const int64_t b0 = rp[i] + d * q / ns, b1 = rp[i] + d * (q + 1) / ns;
+        row.push_back((int32_t)i);
+        beg.push_back(b0);
+        len.push_back((int32_t)(b1 - b0));
+        slot.push_back((int32_t)(slots + q));
+      }
+      slots += ns;
+    }
+  }
+  const int64_t T = (int64_t)row.size();
+  std::vector<int64_t> ord(T);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return len[a] > len[b]; });
+  std::vector<int32_t> srow(T), slen(T), sslot(T);
+  std::vector<int64_t> sbeg(T);
+  for (int64_t x = 0; x < T; ++x) {
+    srow[x] = row[ord[x]];
+    slen[x] = len[ord[x]];
+    sslot[x] = slot[ord[x]];
+    sbeg[x] = beg[ord[x]];
+  }
+  g->n_tasks = T;
+  g->n_slots = slots;
+  g->h_task_len = slen;
+  void *p;
+  ST_TRY(upload(srow, &p, s)); g->task_row = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(slen, &p, s)); g->task_len = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(sslot, &p, s)); g->task_slot = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(sbeg, &p, s)); g->task_beg = (int64_t *)p; g->allocs.push_back(p);
+  g->n_long = (int32_t)lrow.size();
+  ST_TRY(upload(lrow, &p, s)); g->long_row = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(lslot0, &p, s)); g->long_slot0 = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(lnslot, &p, s)); g->long_nslot = (int32_t *)p; g->allocs.push_back(p);
+  HIP_TRY(hipStreamSynchronize(s));
+  return SG2V_OK;
+}
+
+}  // namespace
+
+extern "C" sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *row_ptr,
+                                         const int32_t *col_idx, const float *w, uint32_t flags,
+                                         void *stream, sg2v_graph **out) {
+  if (!out || !row_ptr || (nnz > 0 && !col_idx) || (flags & ~3u)) {
+    set_error("sg2v_graph_create: null argument or unknown flag");
+    return SG2V_EINVAL;
+  }
+  *out = nullptr;
+  if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0) {
+    set_error("sg2v_graph_create: n=%lld nnz=%lld out of range", (long long)n, (long long)nnz);
+    return SG2V_ERANGE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool dev = flags & SG2V_GRAPH_DEVICE_PTRS;
+  std::vector<int64_t> rp(n + 1);
+  std::vector<int32_t> ci;
+  std::vector<float> wv;
+  if (dev) {
+    HIP_TRY(hipMemcpyAsync(rp.data(), row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (flags & SG2V_GRAPH_VALIDATE) {
+      ci.resize(nnz);
+      if (nnz) HIP_TRY(hipMemcpyAsync(ci.data(), col_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    if (w) {
+      wv.resize(nnz);
+      if (nnz) HIP_TRY(hipMemcpyAsync(wv.data(), w, nnz * sizeof(float), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(rp.data(), row_ptr, (n + 1) * sizeof(int64_t));
+  }
+  if (rp[0] != 0 || rp[n] != nnz) {
+    set_error("sg2v_graph_create: row_ptr[0] must be 0 and row_ptr[n] = nnz");
+    return SG2V_EGRAPH;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) {
+      set_error("sg2v_graph_create: row_ptr decreases at row %lld", (long long)i);
+      return SG2V_EGRAPH;
+    }
+  const int32_t *hc = dev ? ci.data() : col_idx;
+  const float *hw = dev ? (w ? wv.data() : nullptr) : w;
+  if (flags & SG2V_GRAPH_VALIDATE) {
+    for (int64_t i = 0; i < n; ++i) {
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        if (hc[e] < 0 || hc[e] >= n || hc[e] == i || (e > rp[i] && hc[e] <= hc[e - 1])) {
+          set_error("sg2v_graph_create: row %lld not sorted/unique/loop-free", (long long)i);
+          return SG2V_EGRAPH;
+        }
+        // symmetric: (j, i) present with the same weight
+        const int64_t j = hc[e];
+        const int32_t *lo = hc + rp[j], *hi = hc + rp[j + 1];
+        const int32_t *f = std::lower_bound(lo, hi, (int32_t)i);
+        if (f == hi || *f != i || (hw && hw[f - hc] != hw[e])) {
+          set_error("sg2v_graph_create: entry (%lld,%lld) has no symmetric partner", (long long)i,
+                    (long long)j);
+          return SG2V_EGRAPH;
+        }
+      }
+    }
+  }
+  std::unique_ptr<sg2v_graph> g(new (std::nothrow) sg2v_graph());
+  if (!g) return SG2V_ENOMEM;
+  HIP_TRY(hipGetDevice(&g->device));
+  g->n = n;
+  g->nnz = nnz;
+  double mw = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double sw = 0.0;
+    if (hw)
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) sw += std::fabs((double)hw[e]);
+    else
+      sw = (double)(rp[i + 1] - rp[i]);
+    mw = std::max(mw, sw);
+  }
+  g->max_wdeg = mw;
+  if (dev) {
+    g->owns = false;
+    g->row_ptr = (int64_t *)row_ptr;
+    g->col_idx = (int32_t *)col_idx;
+    g->w = (float *)w;
+  } else {
+    void *p;
+    HIP_TRY(hipMalloc(&p, (n + 1) * sizeof(int64_t)));
+    g->allocs.push_back(p);
+    g->row_ptr = (int64_t *)p;
+    HIP_TRY(hipMemcpyAsync(p, row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMalloc(&p, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+    g->allocs.push_back(p);
+    g->col_idx = (int32_t *)p;
+    if (nnz) HIP_TRY(hipMemcpyAsync(p, col_idx, nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (w) {
+      HIP_TRY(hipMalloc(&p, std::max<int64_t>(nnz, 1) * sizeof(float)));
+      g->allocs.push_back(p);
+      g->w = (float *)p;
+      if (nnz) HIP_TRY(hipMemcpyAsync(p, w, nnz * sizeof(float), hipMemcpyHostToDevice, s));
+    }
+  }
+  ST_TRY(graph_tasks(g.get(), rp, s));
+  *out = g.release();
+  return SG2V_OK;
+}
+
+extern "C" void sg2v_graph_destroy(sg2v_graph *g) { delete g; }
+
+extern "C" sg2v_status sg2v_color(const sg2v_graph *g, int32_t k, uint64_t seed, int32_t first,
+                                  int32_t n_colorings, void *stream, sg2v_colorings **out) {
+  if (!g || !out || k < 1 || k > SG2V_KMAX || first < 0 || n_colorings < 1 ||
+      (int64_t)first + n_colorings >= (1 << 24)) {
+    set_error("sg2v_color: bad argument (k=%d first=%d count=%d)", k, first, n_colorings);
+    return SG2V_EINVAL;
+  }
+  *out = nullptr;
+  std::unique_ptr<sg2v_colorings> c(new (std::nothrow) sg2v_colorings());
+  if (!c) return SG2V_ENOMEM;
+  c->device = g->device;
+  c->n = g->n;
+  c->k = k;
+  c->count = n_colorings;
+  c->first = first;
+  c->seed = seed;
+  HIP_TRY(hipMalloc((void **)&c->d, g->n * n_colorings));
+  launch_color(c->d, g->n, k, seed, first, n_colorings, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  *out = c.release();
+  return SG2V_OK;
+}
+
+extern "C" void sg2v_colorings_destroy(sg2v_colorings *c) { delete c; }
+
+extern "C" sg2v_status sg2v_colorings_download(const sg2v_colorings *c, uint8_t *out,
+                                               void *stream) {
+  if (!c || !out) {
+    set_error("sg2v_colorings_download: null argument");
+    return SG2V_EINVAL;
+  }
+  HIP_TRY(hipMemcpyAsync(out, c->d, c->n * c->count, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return SG2V_OK;
+}
+
+// ---------------------------------------------------------------------------
+// count
+
+namespace {
+
+struct DevPlan {
+  std::vector<int32_t *> pairs, drop;  // per node, device
+  int32_t *root_list = nullptr;
+};
+
+// device copies of a plan's tables, one per device, kept with the plan
+sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) {
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (auto &d : P.dev)
+    if (d.device == device) {
+      out->pairs.assign(d.pairs.size(), nullptr);
+      out->drop.assign(d.drop.size(), nullptr);
+      for (size_t i = 0; i < d.pairs.size(); ++i) {
+        out->pairs[i] = (int32_t *)d.pairs[i];
+        out->drop[i] = (int32_t *)d.drop[i];
+      }
+      out->root_list = (int32_t *)d.root_list;
+      return SG2V_OK;
+    }
+  Plan::DeviceTables D;
+  D.device = device;
+  D.pairs.assign(P.nodes.size(), nullptr);
+  D.drop.assign(P.nodes.size(), nullptr);
+  for (size_t i = 0; i < P.nodes.size(); ++i) {
+    const Node &nd = P.nodes[i];
+    if (nd.size > 1) {
+      // transpose pairs to [q][C] so that consecutive columns are contiguous
+      std::vector<int32_t> t((size_t)nd.cols * nd.np * 2);
+      for (int64_t C = 0; C < nd.cols; ++C)
+        for (int q = 0; q < nd.np; ++q) {
+          t[((size_t)q * nd.cols + C) * 2 + 0] = nd.pairs[((size_t)C * nd.np + q) * 2 + 0];
+          t[((size_t)q * nd.cols + C) * 2 + 1] = nd.pairs[((size_t)C * nd.np + q) * 2 + 1];
+        }
+      ST_TRY(upload(t, &D.pairs[i], s));
+    }
+    if (!nd.drop.empty()) ST_TRY(upload(nd.drop, &D.drop[i], s));
+  }
+  if (!P.root_list.empty()) ST_TRY(upload(P.root_list, &D.root_list, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  P.dev.push_back(D);
+  return plan_device(P, device, s, out);
+}
+
+enum StepKind { S_HIST, S_SPMM, S_EMA_SINGLE, S_EMA_GENERAL, S_ROOT };
+
+struct Step {
+  StepKind kind;
+  int node;
+};
+
+// one table (M of a node or B of a passive node) within a pass
+struct Tab {
+  int64_t cols = 0;  // columns per colouring
+  int64_t ld = 0;    // row stride in elements
+  int64_t bytes = 0;
+  int first = INT_MAX, last = -1;
+  int64_t off = -1;
+  void *p = nullptr;
+  // FP32S bookkeeping (device)
+  int *e = nullptr;
+  unsigned *mx = nullptr;
+  float *f = nullptr;
+  int *E = nullptr;
+};
+
+struct PassPlan {
+  std::vector<Step> steps;
+  std::vector<Tab> M, B;  // indexed by node
+  int64_t arena = 0;
+  int64_t partial_bytes = 0;
+  int64_t partial_off = 0;
+  int64_t small_bytes = 0;
+  int G = 8;
+};
+
+struct Workspace {
+  DevBuf arena, small, partial, result, ovf;
+};
+
+Workspace &workspace() {
+  static thread_local std::map<int, std::unique_ptr<Workspace>> ws;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto &p = ws[dev];
+  if (!p) p.reset(new Workspace());
+  return *p;
+}
+
+int pick_G(int dt, int64_t widest_cols_b) {
+  sg2v_tuning_t tu = tuning();
+  const int N = dt == DT_F32 ? 4 : 2;
+  int G = 8;  // 128-byte row segments
+  if (tu.spmm_width > 0) G = std::max(2, std::min(16, tu.spmm_width / N));
+  // narrow tables: do not read far past the last column
+  while (G > 2 && (int64_t)G * N / 2 >= widest_cols_b) G /= 2;
+  int p2 = 2;
+  while (p2 * 2 <= G) p2 *= 2;
+  return p2;
+}
+
+// Build the step list and table lifetimes for a pass over b colourings.
+void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots, PassPlan &pp,
+                int debug_node, int debug_kind) {
+  const int es = esize_of(dt);
+  const int N = dt == DT_F32 ? 4 : 2;
+  const int64_t align = std::max<int64_t>(128 / es, (int64_t)G * N);
+  const size_t nn = P.nodes.size();
+  pp.steps.clear();
+  pp.M.assign(nn, Tab());
+  pp.B.assign(nn, Tab());
+  pp.G = G;
+  std::vector<char> haveB(nn, 0);
+  auto needB = [&](int p) {
+    if (haveB[p]) return;
+    haveB[p] = 1;
+    pp.steps.push_back({P.nodes[p].size == 1 ? S_HIST : S_SPMM, p});
+  };
+  for (size_t s = 0; s < nn; ++s) {
+    const Node &nd = P.nodes[s];
+    if (nd.size == 1) continue;
+    const bool is_root = (int)s == P.root;
+    if (is_root) {
+      if (P.root_kind == ROOT_FUSED) needB(P.nodes[nd.active].passive);
+      needB(nd.passive);
+      pp.steps.push_back({S_ROOT, (int)s});
+      continue;
+    }
+    if (P.fused[s] && (int)s != debug_node) continue;
+    needB(nd.passive);
+    pp.steps.push_back({P.nodes[nd.active].size == 1 ? S_EMA_SINGLE : S_EMA_GENERAL, (int)s});
+  }
+  // lifetimes
+  auto touch = [](Tab &t, int step) {
+    t.first = std::min(t.first, step);
+    t.last = std::max(t.last, step);
+  };
+  for (int x = 0; x < (int)pp.steps.size(); ++x) {
+    const Step &st = pp.steps[x];
+    const Node &nd = P.nodes[st.node];
+    switch (st.kind) {
+      case S_HIST: touch(pp.B[st.node], x); break;
+      case S_SPMM: touch(pp.M[st.node], x); touch(pp.B[st.node], x); break;
+      case S_EMA_SINGLE: touch(pp.B[nd.passive], x); touch(pp.M[st.node], x); break;
+      case S_EMA_GENERAL:
+        touch(pp.M[nd.active], x); touch(pp.B[nd.passive], x); touch(pp.M[st.node], x);
+        break;
+      case S_ROOT:
+        if (P.root_kind == ROOT_FUSED) touch(pp.B[P.nodes[nd.active].passive], x);
+        if (P.root_kind == ROOT_GENERAL) touch(pp.M[nd.active], x);
+        touch(pp.B[nd.passive], x);
+        break;
+    }
+  }
+  if (debug_node >= 0) {
+    Tab &t = debug_kind == 0 ? pp.M[debug_node] : pp.B[debug_node];
+    t.last = (int)pp.steps.size();
+  }
+  // sizes
+  std::vector<Tab *> all;
+  for (size_t s = 0; s < nn; ++s) {
+    for (int kind = 0; kind < 2; ++kind) {
+      Tab &t = kind == 0 ? pp.M[s] : pp.B[s];
+      if (t.last < 0) continue;
+      t.cols = P.nodes[s].size == 1 ? P.k : P.nodes[s].cols;
+      t.ld = round_up(t.cols * b, align);
+      t.bytes = round_up(n * t.ld * es, 256);
+      all.push_back(&t);
+    }
+  }
+  // greedy placement: largest first, lowest offset free over the lifetime
+  std::sort(all.begin(), all.end(), [](Tab *a, Tab *c) { return a->bytes > c->bytes; });
+  std::vector<Tab *> placed;
+  int64_t top = 0;
+  for (Tab *t : all) {
+    std::vector<std::pair<int64_t, int64_t>> busy;
+    for (Tab *q : placed)
+      if (!(q->last < t->first || t->last < q->first)) busy.push_back({q->off, q->off + q->bytes});
+    std::sort(busy.begin(), busy.end());
+    int64_t off = 0;
+    for (auto &bz : busy) {
+      if (off + t->bytes <= bz.first) break;
+      off = std::max(off, bz.second);
+    }
+    t->off = off;
+    top = std::max(top, off + t->bytes);
+    placed.push_back(t);
+  }
+  int64_t widest = 0;
+  for (size_t s = 0; s < nn; ++s)
+    if (pp.B[s].last >= 0 && P.nodes[s].size > 1) widest = std::max(widest, pp.B[s].ld);
+  pp.partial_off = top;
+  pp.partial_bytes = round_up(std::max<int64_t>(n_slots, 1) * std::max<int64_t>(widest, 1) * es, 256);
+  pp.arena = top + pp.partial_bytes;
+  // small FP32S arrays: e, mx, f per column, E per colouring
+  int64_t small = 0;
+  for (Tab *t : all) small += round_up(t->cols * b * 12 + b * 4, 256);
+  pp.small_bytes = small + 256;
+}
+
+struct Ctx {
+  const Plan *P;
+  sg2v_graph *g;
+  const sg2v_colorings *c;
+  int dt, es, b, j0;
+  hipStream_t s;
+  DevPlan dp;
+  PassPlan pp;
+  Workspace *ws;
+  int *ovf;
+  int cu_count = 256;
+  size_t lds_max = 65536;
+};
+
+sg2v_status bind_tables(Ctx &x) {
+  char *base = (char *)x.ws->arena.p;
+  char *small = (char *)x.ws->small.p;
+  int64_t so = 0;
+  for (size_t s = 0; s < x.pp.M.size(); ++s) {
+    for (int kind = 0; kind < 2; ++kind) {
+      Tab &t = kind == 0 ? x.pp.M[s] : x.pp.B[s];
+      if (t.last < 0) continue;
+      t.p = base + t.off;
+      if (x.dt == DT_F32) {
+        const int64_t nc = t.cols * x.b;
+        t.e = (int *)(small + so);
+        t.mx = (unsigned *)(small + so + nc * 4);
+        t.f = (float *)(small + so + nc * 8);
+        t.E = (int *)(small + so + nc * 12);
+        so += round_up(nc * 12 + x.b * 4, 256);
+      }
+    }
+  }
+  return SG2V_OK;
+}
+
+// FP32S: column maxima of a freshly produced table -> common frame per colouring
+void norm(Ctx &x, Tab &t) {
+  if (x.dt != DT_F32) return;
+  launch_norm_prep(t.e, t.mx, (int)t.cols, x.b, t.f, t.E, x.s);
+}
+
+sg2v_status step_hist(Ctx &x, int node) {
+  Tab &H = x.pp.B[node];
+  HistArgs a;
+  a.row_ptr = x.g->row_ptr;
+  a.col_idx = x.g->col_idx;
+  a.w = x.g->w;
+  a.colors = x.c->d;
+  a.n = x.g->n;
+  a.k = x.P->k;
+  a.j0 = x.j0;
+  a.b = x.b;
+  a.H = H.p;
+  a.ldh = H.ld;
+  const int64_t blocks = std::min<int64_t>((x.g->n + 3) / 4, 4096);
+  launch_hist(x.dt, a, (int)std::max<int64_t>(blocks, 1), x.s);
+  if (x.dt == DT_U64) launch_zero_pad(x.dt, H.p, x.g->n, H.ld, H.cols * x.b, x.s);
+  if (x.dt == DT_F32) {
+    const int64_t nc = H.cols * x.b;
+    launch_fill_u32((unsigned *)H.e, nc, 0u, x.s);
+    float mw = (float)std::max(1.0, x.g->max_wdeg);
+    unsigned bits;
+    std::memcpy(&bits, &mw, 4);
+    launch_fill_u32(H.mx, nc, bits, x.s);
+    norm(x, H);
+  }
+  return SG2V_OK;
+}
+
+sg2v_status step_spmm(Ctx &x, int node) {
+  Tab &Mp = x.pp.M[node];
+  Tab &B = x.pp.B[node];
+  UnitTable *U = nullptr;
+  ST_TRY(build_units(x.g, x.pp.G, x.s, &U));
+  const int N = x.dt == DT_F32 ? 4 : 2;
+  const int W = x.pp.G * N;
+  const int64_t nc = Mp.cols * x.b;
+  SpmmArgs a;
+  a.col_idx = x.g->col_idx;
+  a.w = x.g->w;
+  a.task_row = x.g->task_row;
+  a.task_beg = x.g->task_beg;
+  a.task_len = x.g->task_len;
+  a.task_slot = x.g->task_slot;
+  a.unit_task = U->unit_task;
+  a.unit_rpw = U->unit_rpw;
+  a.unit_ntask = U->unit_ntask;
+  a.n_units = U->n_units;
+  a.M = Mp.p;
+  a.ldm = Mp.ld;
+  a.B = B.p;
+  a.ldb = B.ld;
+  a.partial = (char *)x.ws->arena.p + x.pp.partial_off;
+  a.ncols_valid = nc;
+  a.mx = x.dt == DT_F32 ? B.mx : nullptr;
+  a.ovf = x.ovf;
+  if (x.dt == DT_F32) launch_fill_u32(B.mx, nc, 0u, x.s);
+  const int64_t chunks = (nc + W - 1) / W;
+  dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
+            (unsigned)chunks);
+  if (launch_spmm(x.dt, a, x.pp.G, grid, x.s)) {
+    set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
+    return SG2V_EINVAL;
+  }
+  CombineArgs cb;
+  cb.partial = a.partial;
+  cb.B = B.p;
+  cb.ld = B.ld;
+  cb.ncols_valid = nc;
+  cb.long_row = x.g->long_row;
+  cb.long_slot0 = x.g->long_slot0;
+  cb.long_nslot = x.g->long_nslot;
+  cb.n_long = x.g->n_long;
+  cb.mx = a.mx;
+  cb.ovf = x.ovf;
+  launch_spmm_combine(x.dt, cb, x.s);
+  if (x.dt == DT_F32) {
+    launch_copy_i32(Mp.e, B.e, nc, x.s);
+    norm(x, B);
+  }
+  return SG2V_OK;
+}
+
+sg2v_status step_ema(Ctx &x, int node, bool single) {
+  const Plan &P = *x.P;
+  const Node &nd = P.nodes[node];
+  Tab &Ms = x.pp.M[node];
+  Tab &Bt = x.pp.B[nd.passive];
+  EmaArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.B = Bt.p;
+  a.ldb = Bt.ld;
+  a.Ms = Ms.p;
+  a.lds = Ms.ld;
+  a.pairs = x.dp.pairs[node];
+  a.drop = x.dp.drop[node];
+  a.np = nd.np;
+  a.Cs = (int32_t)nd.cols;
+  a.Cb = (int32_t)Bt.cols;
+  a.n = x.g->n;
+  a.colors = x.c->d;
+  a.j0 = x.j0;
+  a.ovf = x.ovf;
+  const bool sc = x.dt == DT_F32;
+  if (sc) {
+    a.fb = Bt.f;
+    a.Eb = Bt.E;
+    a.mx = Ms.mx;
+    a.es = Ms.e;
+    launch_fill_u32(Ms.mx, Ms.cols * x.b, 0u, x.s);
+  }
+  const size_t lmx = sc ? (size_t)nd.cols * 4 : 0;
+  if (lmx > x.lds_max) {
+    set_error("sg2v_count: table with %lld columns is too wide for FP32S", (long long)nd.cols);
+    return SG2V_ERANGE;
+  }
+  if (single) {
+    const int64_t cpad = round_up(nd.cols, 64);
+    const int64_t rpi = cpad >= 256 ? 1 : 256 / cpad;
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((x.g->n + rpi - 1) / rpi, 4096)),
+              (unsigned)x.b);
+    launch_ema_single(x.dt, a, grid, lmx, x.s);
+  } else {
+    Tab &Ma = x.pp.M[nd.active];
+    a.Ma = Ma.p;
+    a.lda = Ma.ld;
+    a.Ca = (int32_t)Ma.cols;
+    if (sc) {
+      a.fa = Ma.f;
+      a.Ea = Ma.E;
+    }
+    sg2v_tuning_t tu = tuning();
+    const size_t budget = std::min<size_t>(x.lds_max, 64 * 1024);
+    const size_t rowb = (size_t)((a.Ca | 1) + (a.Cb | 1)) * x.es;
+    int R = 16;
+    if (tu.ema_rows > 0) R = tu.ema_rows;
+    while (R > 1 && R * rowb + lmx > budget) R /= 2;
+    bool stage = R * rowb + lmx <= budget;
+    if (!stage) R = 4;
+    const size_t lds = (stage ? R * rowb : 0) + lmx;
+    const int64_t ntiles = (x.g->n + R - 1) / R;
+    const int64_t per_cu = std::max<int64_t>(1, (int64_t)(x.lds_max / std::max<size_t>(lds, 1)));
+    const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8));
+    dim3 grid((unsigned)std::max<int64_t>(blocks, 1), (unsigned)x.b);
+    if (launch_ema_general(x.dt, a, R, stage, grid, lds, x.s)) {
+      set_error("sg2v_count: no eMA variant for R=%d", R);
+      return SG2V_EINVAL;
+    }
+  }
+  if (x.dt == DT_U64) launch_zero_pad(x.dt, Ms.p, x.g->n, Ms.ld, Ms.cols * x.b, x.s);
+  norm(x, Ms);
+  return SG2V_OK;
+}
+
+// result: per-colouring raw colourful sums (double or uint64) for this pass
+// go to result + j0; FP32S frame exponents to Eout + j0.
+sg2v_status step_root(Ctx &x, int node, void *result, int *Eout);
+
+}  // namespace
+
+
+namespace {
+
+sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
+  const Plan &P = *x.P;
+  const Node &nd = P.nodes[node];
+  RootArgs a;
+  std::memset(&a, 0, sizeof(a));
+  Tab *X = nullptr, *Y = nullptr;
+  if (P.root_kind == ROOT_SINGLE) {
+    X = &x.pp.B[nd.passive];
+  } else if (P.root_kind == ROOT_FUSED) {
+    X = &x.pp.B[P.nodes[nd.active].passive];
+    Y = &x.pp.B[nd.passive];
+  } else {
+    X = &x.pp.M[nd.active];
+    Y = &x.pp.B[nd.passive];
+  }
+  a.X = X->p;
+  a.ldx = X->ld;
+  a.Cx = (int32_t)X->cols;
+  if (Y) {
+    a.Y = Y->p;
+    a.ldy = Y->ld;
+    a.Cy = (int32_t)Y->cols;
+  }
+  a.list = x.dp.root_list;
+  a.L = P.root_L;
+  a.n = x.g->n;
+  a.colors = x.c->d;
+  a.j0 = x.j0;
+  if (x.dt == DT_F32) {
+    a.fx = X->f;
+    a.fy = Y ? Y->f : nullptr;
+  }
+  const int nblk = 1024;
+  a.partial = x.ws->partial.p;
+  a.ovf = x.ovf;
+  launch_root(x.dt, a, dim3(nblk, x.b), x.s);
+  const int es = 8;
+  launch_root_final(x.dt, a.partial, nblk, x.b, (char *)result + (size_t)x.j0 * es, x.ovf, x.s);
+  if (x.dt == DT_F32) launch_root_exp(X->E, Y ? Y->E : nullptr, Eout + x.j0, x.b, x.s);
+  return SG2V_OK;
+}
+
+struct Capture {
+  int node = -1, kind = 0;
+  void *host = nullptr;
+};
+
+sg2v_status copy_capture(Ctx &x, const Capture &cap) {
+  Tab &t = cap.kind == 0 ? x.pp.M[cap.node] : x.pp.B[cap.node];
+  const int64_t n = x.g->n, nc = t.cols;
+  std::vector<char> raw((size_t)n * t.ld * x.es);
+  HIP_TRY(hipMemcpyAsync(raw.data(), t.p, raw.size(), hipMemcpyDeviceToHost, x.s));
+  std::vector<int> e;
+  if (x.dt == DT_F32) {
+    e.resize(nc);
+    HIP_TRY(hipMemcpyAsync(e.data(), t.e, nc * 4, hipMemcpyDeviceToHost, x.s));
+  }
+  HIP_TRY(hipStreamSynchronize(x.s));
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t c = 0; c < nc; ++c) {
+      const size_t src = (size_t)(i * t.ld + c);
+      if (x.dt == DT_U64) {
+        ((uint64_t *)cap.host)[i * nc + c] = ((uint64_t *)raw.data())[src];
+      } else if (x.dt == DT_F64) {
+        ((double *)cap.host)[i * nc + c] = ((double *)raw.data())[src];
+      } else {
+        ((double *)cap.host)[i * nc + c] = std::ldexp((double)((float *)raw.data())[src], e[c]);
+      }
+    }
+  return SG2V_OK;
+}
+
+sg2v_status run_pass(Ctx &x, void *result, int *Eout, const Capture *cap) {
+  for (size_t q = 0; q < x.pp.steps.size(); ++q) {
+    const Step &st = x.pp.steps[q];
+    switch (st.kind) {
+      case S_HIST: ST_TRY(step_hist(x, st.node)); break;
+      case S_SPMM: ST_TRY(step_spmm(x, st.node)); break;
+      case S_EMA_SINGLE: ST_TRY(step_ema(x, st.node, true)); break;
+      case S_EMA_GENERAL: ST_TRY(step_ema(x, st.node, false)); break;
+      case S_ROOT: ST_TRY(step_root(x, st.node, result, Eout)); break;
+    }
+    HIP_TRY(hipGetLastError());
+    if (cap && cap->node == st.node) {
+      const bool produced = (cap->kind == 0 && (st.kind == S_EMA_SINGLE || st.kind == S_EMA_GENERAL)) ||
+                            (cap->kind == 1 && (st.kind == S_HIST || st.kind == S_SPMM));
+      if (produced) ST_TRY(copy_capture(x, *cap));
+    }
+  }
+  return SG2V_OK;
+}
+
+sg2v_status check_inputs(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
+                         sg2v_mode mode) {
+  if (!plan || !g || !c) {
+    set_error("sg2v_count: null handle");
+    return SG2V_EINVAL;
+  }
+  if (mode != SG2V_FP64 && mode != SG2V_FP32S && mode != SG2V_U64) {
+    set_error("sg2v_count: unknown mode %d", mode);
+    return SG2V_EINVAL;
+  }
+  if (c->k != plan->p.k || c->n != g->n) {
+    set_error("sg2v_count: colourings have k=%d n=%lld, plan k=%d graph n=%lld", c->k,
+              (long long)c->n, plan->p.k, (long long)g->n);
+    return SG2V_EINVAL;
+  }
+  if (mode == SG2V_U64 && g->w) {
+    set_error("sg2v_count: U64 mode counts the 0/1 adjacency; the graph has weights");
+    return SG2V_EINVAL;
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->device || dev != c->device) {
+    set_error("sg2v_count: current device %d differs from the graph's (%d)", dev, g->device);
+    return SG2V_EINVAL;
+  }
+  return SG2V_OK;
+}
+
+int choose_batch(const Plan &P, int ncol, int dt, int64_t n, int64_t n_slots) {
+  sg2v_tuning_t tu = tuning();
+  int64_t widest_passive = 1;
+  for (auto &nd : P.nodes)
+    if (nd.n_passive_uses > 0) widest_passive = std::max(widest_passive, nd.size == 1 ? P.k : nd.cols);
+  int b = tu.batch > 0 ? tu.batch : (int)std::max<int64_t>(1, 1024 / widest_passive);
+  b = std::max(1, std::min(b, ncol));
+  // memory budget
+  size_t fr = 0, tot = 0;
+  (void)hipMemGetInfo(&fr, &tot);
+  int64_t budget = tu.budget_bytes > 0 ? tu.budget_bytes : (int64_t)(fr * 0.85);
+  while (b > 1) {
+    PassPlan pp;
+    build_pass(P, n, b, dt, pick_G(dt, widest_passive * b), n_slots, pp, -1, 0);
+    if (pp.arena <= budget) break;
+    b = (b + 1) / 2;
+  }
+  return b;
+}
+
+sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_colorings *c,
+                    sg2v_mode mode, int b, hipStream_t s, int debug_node, int debug_kind) {
+  x.P = &plan->p;
+  x.g = g;
+  x.c = c;
+  x.dt = dtype_of(mode);
+  x.es = esize_of(x.dt);
+  x.b = b;
+  x.s = s;
+  x.ws = &workspace();
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, g->device));
+  x.cu_count = prop.multiProcessorCount;
+  x.lds_max = prop.sharedMemPerBlock;
+  ST_TRY(plan_device(plan->p, g->device, s, &x.dp));
+  int64_t widest = 1;
+  for (auto &nd : plan->p.nodes)
+    if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? plan->p.k : nd.cols);
+  build_pass(plan->p, g->n, b, x.dt, pick_G(x.dt, widest * b), g->n_slots, x.pp, debug_node,
+             debug_kind);
+  sg2v_tuning_t tu = tuning();
+  if (tu.budget_bytes > 0 && x.pp.arena > tu.budget_bytes) {
+    set_error("sg2v_count: one colouring needs %lld bytes, budget is %lld",
+              (long long)x.pp.arena, (long long)tu.budget_bytes);
+    return SG2V_ENOMEM;
+  }
+  ST_TRY(x.ws->arena.ensure(x.pp.arena));
+  ST_TRY(x.ws->small.ensure(x.pp.small_bytes));
+  ST_TRY(x.ws->partial.ensure((size_t)1024 * b * 8));
+  ST_TRY(x.ws->ovf.ensure(256));
+  x.ovf = (int *)x.ws->ovf.p;
+  return bind_tables(x);
+}
+
+}  // namespace
+
+extern "C" sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g,
+                                  const sg2v_colorings *c, sg2v_mode mode, void *stream,
+                                  double *colorful, uint64_t *colorful_u64, double *estimate,
+                                  double *mean_estimate, int32_t *overflow) {
+  ST_TRY(check_inputs(plan, g, c, mode));
+  const Plan &P = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  const int ncol = c->count;
+  std::vector<double> raw_f(ncol, 0.0);
+  std::vector<uint64_t> raw_u(ncol, 0);
+  std::vector<int> Eh(ncol, 0);
+  int ovf_h = 0;
+  if (P.root_kind == ROOT_VERTEX) {
+    for (int j = 0; j < ncol; ++j) {
+      raw_f[j] = (double)g->n;  // every vertex is one colourful map of a one-vertex template
+      raw_u[j] = (uint64_t)g->n;
+    }
+  } else {
+    const int dt = dtype_of(mode);
+    const int b = choose_batch(P, ncol, dt, g->n, g->n_slots);
+    Ctx x;
+    ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, b, s, -1, 0));
+    ST_TRY(x.ws->result.ensure((size_t)ncol * 12 + 64));
+    void *res = x.ws->result.p;
+    int *Ed = (int *)((char *)res + (size_t)ncol * 8);
+    launch_fill_u32((unsigned *)x.ovf, 1, 0u, s);
+    for (int j0 = 0; j0 < ncol; j0 += b) {
+      const int bb = std::min(b, ncol - j0);
+      if (bb != x.b) {
+        // last, smaller pass: tables of the full batch still fit
+        x.b = bb;
+        build_pass(P, g->n, bb, x.dt, x.pp.G, g->n_slots, x.pp, -1, 0);
+        ST_TRY(bind_tables(x));
+      }
+      x.j0 = j0;
+      ST_TRY(run_pass(x, res, Ed, nullptr));
+    }
+    if (dt == DT_U64) {
+      HIP_TRY(hipMemcpyAsync(raw_u.data(), res, ncol * 8, hipMemcpyDeviceToHost, s));
+    } else {
+      HIP_TRY(hipMemcpyAsync(raw_f.data(), res, ncol * 8, hipMemcpyDeviceToHost, s));
+    }
+    if (dt == DT_F32) HIP_TRY(hipMemcpyAsync(Eh.data(), Ed, ncol * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ovf_h, x.ovf, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (dt == DT_U64)
+      for (int j = 0; j < ncol; ++j) raw_f[j] = (double)raw_u[j];
+    if (dt == DT_F32)
+      for (int j = 0; j < ncol; ++j) raw_f[j] = std::ldexp(raw_f[j], Eh[j]);
+  }
+  double mean = 0.0;
+  for (int j = 0; j < ncol; ++j) {
+    if (colorful) colorful[j] = raw_f[j];
+    if (colorful_u64) colorful_u64[j] = raw_u[j];
+    const double est = raw_f[j] / (P.P * (double)P.alpha);
+    if (estimate) estimate[j] = est;
+    mean += est;
+  }
+  if (mean_estimate) *mean_estimate = mean / ncol;
+  if (overflow) *overflow = ovf_h;
+  return SG2V_OK;
+}
+
+extern "C" sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph *g,
+                                        const sg2v_colorings *c, sg2v_mode mode, int32_t which,
+                                        int32_t node, int32_t kind, void *host_out, void *stream) {
+  ST_TRY(check_inputs(plan, g, c, mode));
+  const Plan &P = plan->p;
+  if (!host_out || which < 0 || which >= c->count || node < 0 || node >= (int)P.nodes.size() ||
+      (kind != 0 && kind != 1)) {
+    set_error("sg2v_debug_table: bad argument");
+    return SG2V_EINVAL;
+  }
+  const Node &nd = P.nodes[node];
+  if ((kind == 0 && (nd.size == 1 || node == P.root)) || (kind == 1 && nd.n_passive_uses == 0)) {
+    set_error("sg2v_debug_table: node %d has no materialised %s table", node, kind ? "B" : "M");
+    return SG2V_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Ctx x;
+  ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, 1, s, node, kind));
+  ST_TRY(x.ws->result.ensure((size_t)c->count * 12 + 64));
+  void *res = x.ws->result.p;
+  int *Ed = (int *)((char *)res + (size_t)c->count * 8);
+  launch_fill_u32((unsigned *)x.ovf, 1, 0u, s);
+  x.j0 = which;
+  Capture cap;
+  cap.node = node;
+  cap.kind = kind;
+  cap.host = host_out;
+  ST_TRY(run_pass(x, res, Ed, &cap));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SG2V_OK;
+}
+
+extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n_plans,
+                                        const sg2v_graph *g, uint64_t seed, int32_t n_colorings,
+                                        sg2v_mode mode, void *stream, double *colorful,
+                                        double *estimate) {
+  if (!plans || n_plans < 1 || !g || n_colorings < 1) {
+    set_error("sg2v_count_batch: bad argument");
+    return SG2V_EINVAL;
+  }
+  for (int p = 0; p < n_plans; ++p) {
+    sg2v_colorings *c = nullptr;
+    ST_TRY(sg2v_color(g, plans[p]->p.k, seed, 0, n_colorings, stream, &c));
+    std::unique_ptr<sg2v_colorings> hold(c);
+    ST_TRY(sg2v_count(plans[p], g, c, mode, stream, colorful ? colorful + (size_t)p * n_colorings : nullptr,
+                      nullptr, estimate ? estimate + (size_t)p * n_colorings : nullptr, nullptr,
+                      nullptr));
+  }
+  return SG2V_OK;
+}
+
+extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *, const sg2v_graph *,
+                                       const sg2v_colorings *, sg2v_mode, const double *, void *,
+                                       void *) {
+  set_error("sg2v_count_grad: not available in this build");
+  return SG2V_EINVAL;
+}
+
+extern "C" sg2v_status sg2v_set_tuning(const sg2v_tuning_t *t) {
+  if (!t) {
+    set_error("sg2v_set_tuning: null");
+    return SG2V_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune = *t;
+  return SG2V_OK;
+}
+
+extern "C" sg2v_status sg2v_get_tuning(sg2v_tuning_t *t) {
+  if (!t) {
+    set_error("sg2v_get_tuning: null");
+    return SG2V_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  *t = g_tune;
+  return SG2V_OK;
+}
+
+extern "C" void sg2v_plan_destroy(sg2v_plan *plan) {
+  if (!plan) return;
+  for (auto &d : plan->p.dev) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(d.device);
+    for (void *q : d.pairs) (void)hipFree(q);
+    for (void *q : d.drop) (void)hipFree(q);
+    (void)hipFree(d.root_list);
+    (void)hipSetDevice(cur);
+  }
+  delete plan;
+}

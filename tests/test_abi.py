@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function its header declares, the planner's partition, split
+tables, alpha and P agree with independent enumerations and the oracle, and
+malformed inputs are rejected with the documented status codes."""
+import math
+import os
+import re
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle as O
+import paper_2009_11665_amd as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sg2v.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg2v_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = sg.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(sg.EXPORTS)
+    assert "gfx950" in sg.version()
+
+
+def colex_rank(s):
+    return sum(math.comb(c, i + 1) for i, c in enumerate(sorted(s)))
+
+
+def test_colex_order_matches_oracle_mask_order():
+    # the oracle indexes colour sets by increasing mask; colex rank must agree
+    k = 9
+    for m in range(1, k + 1):
+        sets = sorted(combinations(range(k), m), key=lambda s: sum(1 << c for c in s))
+        assert [colex_rank(s) for s in sets] == list(range(math.comb(k, m)))
+
+
+TEMPLATES = [gg.PATH5, gg.BINTREE7, gg.CATERPILLAR10, gg.PATH8, gg.BINTREE15, [-1, 0, 0, 0],
+             [-1, 0], [-1], [2, 2, -1, 0, 0, 1, 3]]
+
+
+@pytest.mark.parametrize("par", TEMPLATES)
+def test_plan_alpha_and_probability(par):
+    t = len(par)
+    for k in sorted({t, t + 1, min(t + 3, 20)}):
+        p = sg.Plan(par, k)
+        info = p.info()
+        assert info.alpha == O.automorphisms(par)
+        assert info.colorful_prob == pytest.approx(O.colorful_probability(t, k), rel=1e-14)
+        assert info.t == t and info.k == k
+
+
+@pytest.mark.parametrize("par", TEMPLATES)
+def test_split_tables_enumerate_every_split_once(par):
+    t = len(par)
+    k = min(t + 1, 20) if t < 12 else t
+    p = sg.Plan(par, k)
+    nodes = p.nodes()
+    for idx, nd in enumerate(nodes):
+        assert nd.columns == math.comb(k, nd.size)
+        if nd.size == 1:
+            continue
+        A, Pn = nodes[nd.active], nodes[nd.passive]
+        assert A.size + Pn.size == nd.size
+        pairs = p.pairs(idx)
+        out_sets = sorted(combinations(range(k), nd.size), key=colex_rank)
+        for r, C in enumerate(out_sets):
+            expect = set()
+            for S in combinations(C, A.size):
+                expect.add((colex_rank(S), colex_rank(set(C) - set(S))))
+            got = {(int(a), int(b)) for a, b in pairs[r]}
+            assert got == expect and len(pairs[r]) == len(expect)
+
+
+def test_bintree15_partition_shape():
+    """The 15-vertex complete binary tree splits into 6 distinct sub-templates
+    (sizes 2, 3, 4, 7, 8, 15) with 3 distinct passive children."""
+    p = sg.Plan(gg.BINTREE15, 15)
+    info = p.info()
+    assert info.n_splits == 6 and info.n_passive == 3
+    assert info.spmm_columns == 15 + 455 + 6435
+    assert info.pairs_per_vertex == 210 + 1365 + 5460 + 225225 + 51480 + 6435
+    assert info.widest_table == 6435
+    sizes = sorted(nd.size for nd in p.nodes())
+    assert sizes == [1, 2, 3, 4, 7, 8, 15]
+
+
+def test_dedup_preserves_first_occurrence():
+    p = sg.Plan(gg.BINTREE7, 7)
+    for nd in p.nodes():
+        # (vertex, n_kept) is a valid sub-template of the input
+        assert 0 <= nd.vertex < 7
+
+
+@pytest.mark.parametrize("bad,t,k,status", [
+    ([-1, -1, 0], 3, 3, -2), ([0, 1, 2], 3, 3, -2), ([-1, 0, 5], 3, 3, -2),
+    ([-1, 2, 1], 3, 3, -2), ([-1, 0, 1], 3, 2, -3), ([-1] + [0] * 20, 21, 21, -3)])
+def test_plan_rejects_bad_input(bad, t, k, status):
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.Plan(bad, k)
+    assert e.value.status == status
+    assert len(sg.lib().sg2v_last_error()) > 0
+
+
+def test_graph_validation_errors_on_host():
+    # these are detected before any device call
+    rp = np.array([0, 2, 3, 4], np.int64)
+    ci = np.array([1, 1, 0, 0], np.int32)  # duplicate in row 0
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.Graph(3, rp, ci, validate=True)
+    assert e.value.status == -5
+    rp = np.array([0, 1, 1], np.int64)
+    ci = np.array([1], np.int32)  # (0,1) without (1,0)
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.Graph(2, rp, ci, validate=True)
+    assert e.value.status == -5
+    rp = np.array([0, 1, 2], np.int64)
+    ci = np.array([0, 1], np.int32)  # self-loops
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.Graph(2, rp, ci, validate=True)
+    assert e.value.status == -5
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.Graph(2, np.array([1, 1, 1], np.int64), np.zeros(0, np.int32))
+    assert e.value.status == -5
+
+
+def test_tuning_roundtrip():
+    old = sg.get_tuning()
+    try:
+        sg.set_tuning(spmm_width=64, ema_rows=8, batch=3, budget_bytes=123456)
+        t = sg.get_tuning()
+        assert (t.spmm_width, t.ema_rows, t.batch, t.budget_bytes) == (64, 8, 3, 123456)
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes)

@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path through the C ABI against the oracle on the same
+seeded inputs.  Exact for U64 and colours, relative 1e-12 for FP64 and 1e-5
+for FP32 with per-column scaling (against the FP64 oracle)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle as O
+import paper_2009_11665_amd as sg
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def random_tree(t, rng):
+    par = [-1] + [int(rng.integers(0, v)) for v in range(1, t)]
+    perm = rng.permutation(t)
+    out = [0] * t
+    for v in range(t):
+        out[perm[v]] = -1 if par[v] < 0 else int(perm[par[v]])
+    return out
+
+
+def gpu_counts(G, par, k, seed, ncol, mode, weighted=None):
+    g = sg.Graph.from_csr(G, weighted=weighted)
+    c = sg.Colorings(g, k, seed, ncol)
+    return sg.count(sg.Plan(par, k), g, c, mode)
+
+
+def oracle_counts(G, par, k, seed, ncol, mode=O.FP64, weights=None):
+    out = []
+    for j in range(ncol):
+        col = O.colors(G.n, k, seed, j)
+        out.append(O.count(G, par, k, col, mode=mode, weights=weights))
+    return out
+
+
+@pytest.fixture(scope="module")
+def small_rmat():
+    return gg.rmat(11, 12_000, seed=21)
+
+
+def test_colors_match_oracle():
+    G = gg.tiny_er()
+    g = sg.Graph.from_csr(G)
+    for k, seed in ((5, 1), (15, 7), (20, 123456789)):
+        c = sg.Colorings(g, k, seed, 3, first=2).download()
+        for j in range(3):
+            np.testing.assert_array_equal(c[j], O.colors(G.n, k, seed, 2 + j))
+    G2 = gg.rmat16()
+    c = sg.Colorings(sg.Graph.from_csr(G2), 7, 99, 1).download()
+    np.testing.assert_array_equal(c[0], O.colors(G2.n, 7, 99, 0))
+
+
+def test_tiny_config_all_modes():
+    """path5 on ER(1000, 4000), k = 5: exact vs oracle and brute force."""
+    G = gg.tiny_er()
+    col = O.colors(G.n, 5, 1, 0)
+    _, bc, _ = O.brute(G, gg.PATH5, col)
+    ou = O.count(G, gg.PATH5, 5, col, mode=O.U64)
+    r = gpu_counts(G, gg.PATH5, 5, 1, 1, "u64")
+    say("tiny u64", r["colorful_u64"][0], ou[1], bc)
+    assert int(r["colorful_u64"][0]) == ou[1] == bc and not r["overflow"]
+    r64 = gpu_counts(G, gg.PATH5, 5, 1, 1, "fp64")
+    assert r64["colorful"][0] == pytest.approx(float(bc), rel=FP64_TOL)
+    r32 = gpu_counts(G, gg.PATH5, 5, 1, 1, "fp32s")
+    assert r32["colorful"][0] == pytest.approx(float(bc), rel=FP32_TOL)
+    est = bc / (O.colorful_probability(5, 5) * 2)
+    assert r64["estimate"][0] == pytest.approx(est, rel=FP64_TOL)
+
+
+TEMPLATES = [gg.PATH5, gg.BINTREE7, gg.CATERPILLAR10, [-1, 0, 0, 0], [-1, 0], [-1, 0, 0, 1, 1],
+             [-1, 0, 0, 0, 0, 0]]
+
+
+@pytest.mark.parametrize("ti", range(len(TEMPLATES)))
+def test_templates_u64_exact(small_rmat, ti):
+    par = TEMPLATES[ti]
+    t = len(par)
+    for k in (t, t + 1):
+        say("u64 template", par, "k", k)
+        r = gpu_counts(small_rmat, par, k, 5, 3, "u64")
+        for j, (f, u, ov) in enumerate(oracle_counts(small_rmat, par, k, 5, 3, O.U64)):
+            assert int(r["colorful_u64"][j]) == u, (par, k, j)
+        assert r["overflow"] == any(x[2] for x in oracle_counts(small_rmat, par, k, 5, 3, O.U64))
+
+
+def test_random_trees_all_modes(small_rmat):
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        t = int(rng.integers(2, 9))
+        par = random_tree(t, rng)
+        k = t + int(rng.integers(0, 3))
+        say("random tree", par, "k", k)
+        ref = oracle_counts(small_rmat, par, k, 11, 2, O.U64)
+        ref64 = oracle_counts(small_rmat, par, k, 11, 2, O.FP64)
+        ru = gpu_counts(small_rmat, par, k, 11, 2, "u64")
+        r64 = gpu_counts(small_rmat, par, k, 11, 2, "fp64")
+        r32 = gpu_counts(small_rmat, par, k, 11, 2, "fp32s")
+        for j in range(2):
+            assert int(ru["colorful_u64"][j]) == ref[j][1]
+            assert r64["colorful"][j] == pytest.approx(ref64[j][0], rel=FP64_TOL)
+            assert r32["colorful"][j] == pytest.approx(ref64[j][0], rel=FP32_TOL)
+
+
+@pytest.mark.parametrize("mode", ["u64", "fp64", "fp32s"])
+def test_intermediate_tables(small_rmat, mode):
+    """Every materialised table M_s and B = A M_p against the oracle's."""
+    G = small_rmat
+    for par, k in ((gg.BINTREE7, 7), (gg.CATERPILLAR10, 10)):
+        p = sg.Plan(par, k)
+        g = sg.Graph.from_csr(G)
+        c = sg.Colorings(g, k, 3, 2)
+        col1 = O.colors(G.n, k, 3, 1)
+        om = O.U64 if mode == "u64" else O.FP64
+        info = p.info()
+        for idx, nd in enumerate(p.nodes()):
+            ref_M = O.node_table(G, par, k, col1, nd.vertex, nd.n_kept, mode=om)
+            if nd.size > 1 and idx != info.root_node:
+                say("table M", par, idx, mode)
+                got = sg.debug_table(p, g, c, idx, 0, which=1, mode=mode)
+                _cmp(got, ref_M, mode)
+            if nd.is_passive:
+                say("table B", par, idx, mode)
+                got = sg.debug_table(p, g, c, idx, 1, which=1, mode=mode)
+                _cmp(got, O.neighbour_sum(G, ref_M, mode=om), mode)
+
+
+def _cmp(got, ref, mode):
+    assert got.shape == ref.shape
+    if mode == "u64":
+        np.testing.assert_array_equal(got, ref)
+    else:
+        tol = FP64_TOL if mode == "fp64" else FP32_TOL
+        np.testing.assert_allclose(got, ref, rtol=tol, atol=tol * max(1.0, float(np.abs(ref).max())) * 1e-3)
+
+
+def test_weighted_counts():
+    G = gg.chung_lu(6000, 10.0, 2.1, seed=8, weighted=True)
+    for par in (gg.CATERPILLAR10, gg.PATH5):
+        k = len(par)
+        say("weighted", par)
+        ref = oracle_counts(G, par, k, 4, 2)
+        r64 = gpu_counts(G, par, k, 4, 2, "fp64")
+        r32 = gpu_counts(G, par, k, 4, 2, "fp32s")
+        for j in range(2):
+            assert r64["colorful"][j] == pytest.approx(ref[j][0], rel=FP64_TOL)
+            assert r32["colorful"][j] == pytest.approx(ref[j][0], rel=FP32_TOL)
+
+
+def test_batching_invariance(small_rmat):
+    """Colourings as extra columns (batch > 1) give the same counts as one
+    colouring per pass."""
+    par, k = gg.BINTREE7, 7
+    g = sg.Graph.from_csr(small_rmat)
+    c = sg.Colorings(g, k, 17, 5)
+    p = sg.Plan(par, k)
+    old = sg.get_tuning()
+    try:
+        res = {}
+        for b in (1, 2, 5):
+            sg.set_tuning(batch=b)
+            res[b] = sg.count(p, g, c, "u64")["colorful_u64"].copy()
+            res[("f", b)] = sg.count(p, g, c, "fp32s")["colorful"].copy()
+        np.testing.assert_array_equal(res[1], res[2])
+        np.testing.assert_array_equal(res[1], res[5])
+        np.testing.assert_allclose(res[("f", 1)], res[("f", 5)], rtol=1e-6)
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes)
+
+
+def test_spmm_widths_agree(small_rmat):
+    par, k = gg.CATERPILLAR10, 10
+    g = sg.Graph.from_csr(small_rmat)
+    c = sg.Colorings(g, k, 2, 2)
+    p = sg.Plan(par, k)
+    ref = [x[1] for x in oracle_counts(small_rmat, par, k, 2, 2, O.U64)]
+    old = sg.get_tuning()
+    try:
+        for w in (8, 16, 32, 64):
+            sg.set_tuning(spmm_width=w)
+            say("spmm width", w)
+            got = sg.count(p, g, c, "u64")["colorful_u64"]
+            assert [int(x) for x in got] == ref
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes)
+
+
+def test_edge_cases():
+    # isolated vertices only
+    G0 = gg.from_edge_list(50, [])
+    g0 = sg.Graph.from_csr(G0)
+    for par in (gg.PATH5, [-1, 0]):
+        r = sg.count(sg.Plan(par), g0, sg.Colorings(g0, len(par), 1, 2), "u64")
+        assert list(r["colorful_u64"]) == [0, 0]
+    # one-vertex template: every vertex is one map
+    G = gg.tiny_er()
+    g = sg.Graph.from_csr(G)
+    r = sg.count(sg.Plan([-1], 1), g, sg.Colorings(g, 1, 1, 1), "fp64")
+    assert r["colorful"][0] == G.n
+    # fewer vertices than a tile, ragged sizes
+    Gs = gg.from_edge_list(7, [(0, 1), (1, 2), (2, 3), (3, 4), (1, 5), (5, 6), (0, 6)])
+    for par in (gg.PATH5, [-1, 0, 0]):
+        t = len(par)
+        ref = oracle_counts(Gs, par, t, 3, 4, O.U64)
+        r = gpu_counts(Gs, par, t, 3, 4, "u64")
+        assert [int(x) for x in r["colorful_u64"]] == [x[1] for x in ref]
+
+
+def test_long_rows_split_across_tasks():
+    """Rows longer than one SpMM task are split and their partial rows summed."""
+    rng = np.random.default_rng(9)
+    n = 12_000
+    edges = {(0, v) for v in range(1, 9001)} | {(1, v) for v in range(2, 5002)}
+    while len(edges) < 30_000:
+        a, b = (int(x) for x in rng.integers(0, n, 2))
+        if a != b:
+            edges.add((min(a, b), max(a, b)))
+    G = gg.from_edge_list(n, sorted(edges))
+    for par in (gg.PATH5, gg.BINTREE7):
+        k = len(par)
+        say("long rows", par)
+        ref = oracle_counts(G, par, k, 6, 2, O.U64)
+        ref64 = oracle_counts(G, par, k, 6, 2, O.FP64)
+        r = gpu_counts(G, par, k, 6, 2, "u64")
+        r32 = gpu_counts(G, par, k, 6, 2, "fp32s")
+        for j in range(2):
+            assert int(r["colorful_u64"][j]) == ref[j][1]
+            assert r32["colorful"][j] == pytest.approx(ref64[j][0], rel=FP32_TOL)
+
+
+def test_u64_overflow_flag():
+    D, t = 1200, 12
+    G = gg.from_edge_list(D + 1, [(0, v) for v in range(1, D + 1)])
+    par = [-1] + [0] * (t - 1)
+    col = O.colors(G.n, t, 5, 0)
+    f, u, ov = O.count(G, par, t, col, mode=O.U64)
+    r = gpu_counts(G, par, t, 5, 1, "u64")
+    assert ov and r["overflow"] and int(r["colorful_u64"][0]) == u
+    r64 = gpu_counts(G, par, t, 5, 1, "fp64")
+    f64, _, _ = O.count(G, par, t, col)
+    assert r64["colorful"][0] == pytest.approx(f64, rel=FP64_TOL)
+
+
+def test_mid_config_rmat16_bintree7():
+    """RMAT scale 16 (nnz 2,097,152), bintree7, k = 7, 8 colourings:
+    FP32S within 1e-5 of the FP64 oracle; U64 exact (mod 2^64)."""
+    G = gg.rmat16()
+    par, k, seed, ncol = gg.BINTREE7, 7, 2, 8
+    ref = oracle_counts(G, par, k, seed, ncol)
+    refu = oracle_counts(G, par, k, seed, ncol, O.U64)
+    r32 = gpu_counts(G, par, k, seed, ncol, "fp32s")
+    ru = gpu_counts(G, par, k, seed, ncol, "u64")
+    r64 = gpu_counts(G, par, k, seed, ncol, "fp64")
+    for j in range(ncol):
+        say("mid", j, r32["colorful"][j], ref[j][0])
+        assert r32["colorful"][j] == pytest.approx(ref[j][0], rel=FP32_TOL)
+        assert r64["colorful"][j] == pytest.approx(ref[j][0], rel=FP64_TOL)
+        assert int(ru["colorful_u64"][j]) == refu[j][1]
+    assert ru["overflow"] == any(x[2] for x in refu)
+
+
+def test_bintree15_on_rmat14_against_oracle():
+    """The large configuration's template (15-vertex binary tree, k = 15) on a
+    smaller RMAT graph that the oracle finishes: FP32S and FP64 vs oracle."""
+    G = gg.rmat(12, 60_000, seed=5)
+    par, k = gg.BINTREE15, 15
+    ref = oracle_counts(G, par, k, 5, 1)
+    r64 = gpu_counts(G, par, k, 5, 1, "fp64")
+    r32 = gpu_counts(G, par, k, 5, 1, "fp32s")
+    say("bt15", ref[0][0], r64["colorful"][0], r32["colorful"][0])
+    assert ref[0][0] > 0
+    assert r64["colorful"][0] == pytest.approx(ref[0][0], rel=FP64_TOL)
+    assert r32["colorful"][0] == pytest.approx(ref[0][0], rel=FP32_TOL)
