@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark: colourings/s of the batched FP32 (per-column scaled) count of
+the 15-vertex complete binary tree on an RMAT graph with 2^20 vertices and
+200,000,000 directed edges (k = 15, 4 colourings per step), next to the plain
+one-colouring-per-pass FP64 path and the CPU oracle.
+
+One step = colour the graph 4 times and run the whole dynamic programme
+(neighbour-colour histogram, SpMMs, multiply-adds, root reduction) for all 4
+colourings; inputs are resident in HBM when the timed region starts.
+
+Prints one JSON line.  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "colorings/s batched FP32 vs plain FP64, RMAT-1M 15-vertex tree; HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2009_11665_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_traffic_bintree15_rmat20.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def oracle_work(parent, k, n, nnz):
+    """Inner-loop iterations of the oracle for one colouring: for every split
+    of its (non-deduplicated, last-child) partition, n * C(k,m) * 2^m sub-mask
+    steps and nnz * C(k, m_p) neighbour additions."""
+    t = len(parent)
+    ch = [[] for _ in range(t)]
+    root = parent.index(-1)
+    for v, p in enumerate(parent):
+        if p >= 0:
+            ch[p].append(v)
+
+    def size(v):
+        return 1 + sum(size(c) for c in ch[v])
+
+    work = 0
+
+    def walk(v, kept):
+        nonlocal work
+        if kept == 0:
+            return 1
+        m_a = walk(v, kept - 1)
+        tau = ch[v][kept - 1]
+        m_p = walk(tau, len(ch[tau]))
+        m = m_a + m_p
+        work += n * math.comb(k, m) * (1 << m) + nnz * math.comb(k, m_p)
+        return m
+
+    walk(root, len(ch[root]))
+    return work
+
+
+def kernel_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per SpMM launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha") != kernel_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(parent, k, scale, seed, full_n, full_nnz):
+    """The oracle (FP64, OpenMP over vertices) on a bounded sample: the same
+    template and colouring rule on an RMAT graph of 2^scale vertices with the
+    full graph's average degree; scaled to the full graph by the oracle's
+    inner-loop count."""
+    import graphgen as gg
+    import oracle as O
+
+    avg = full_nnz / full_n
+    m = int(round(avg / 2 * (1 << scale)))
+    G = gg.rmat(scale, m, seed=seed)
+    col = O.colors(G.n, k, seed, 0)
+    t0 = time.perf_counter()
+    O.count(G, parent, k, col)
+    dt = time.perf_counter() - t0
+    ratio = oracle_work(parent, k, full_n, full_nnz) / oracle_work(parent, k, G.n, G.nnz)
+    return {
+        "value": 1.0 / (dt * ratio),
+        "unit": "colorings/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"1 colouring of bintree15 (k={k}) on RMAT scale {scale} "
+                   f"(n={G.n}, nnz={G.nnz}, same average degree) took {dt:.2f} s; scaled by the "
+                   f"oracle's inner-loop count to the full graph (x{ratio:.1f})"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--colorings", type=int, default=4)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--edges", type=int, default=100_000_000, help="undirected edges")
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--cpu-scale", type=int, default=14)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
+                          "sharding of the count is a design, not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import graphgen as gg
+    import paper_2009_11665_amd as sg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    parent, k, ncol = gg.BINTREE15, 15, args.colorings
+
+    t0 = time.perf_counter()
+    G = gg.rmat(args.scale, args.edges, seed=args.seed)
+    log(f"graph: RMAT scale {args.scale}, n={G.n}, nnz={G.nnz}, max deg {int(G.degrees().max())} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    g = sg.Graph.from_csr(G)
+    plan = sg.Plan(parent, k)
+    info = plan.info()
+    torch.cuda.synchronize()
+
+    def step(mode, first):
+        c = sg.Colorings(g, k, args.seed, ncol, first=first)
+        return sg.count(plan, g, c, mode)
+
+    # batched FP32 with per-column exponents
+    for w in range(args.warmup):
+        step("fp32s", 1000 + w * ncol)
+        log(f"warmup step {w} done")
+    torch.cuda.synchronize()
+    sg.profile_start()
+    t0 = time.perf_counter()
+    res32 = None
+    for s in range(args.steps):
+        res32 = step("fp32s", s * ncol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sg.profile_stop()
+    log(f"timed {args.steps} fp32s steps: {(t1 - t0) / args.steps * 1e3:.1f} ms/step")
+    ms_step = (t1 - t0) / args.steps * 1e3
+    value = ncol * args.steps / (t1 - t0)
+
+    # plain per-colouring FP64 on the colourings of the last timed step
+    fp64 = None
+    err = None
+    if not args.no_fp64:
+        old = sg.get_tuning()
+        sg.set_tuning(old.spmm_width, old.ema_rows, 1, old.budget_bytes)
+        try:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            r64 = None
+            for s in range(args.fp64_steps):
+                r64 = step("fp64", (args.steps - 1) * ncol)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+        finally:
+            sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes)
+        fp64 = {"value": ncol * args.fp64_steps / (t3 - t2), "unit": "colorings/s",
+                "ms_per_step": (t3 - t2) / args.fp64_steps * 1e3}
+        err = max(abs(a - b) / abs(b) for a, b in zip(res32["colorful"], r64["colorful"]) if b)
+        log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, fp32s rel err {err:.2e}")
+
+    sp = prof["spmm"]
+    achieved = sp["bytes"] / (sp["ms"] * 1e-3) / 1e9 if sp["ms"] > 0 else 0.0
+    traffic = load_traffic()
+    total_bytes = sum(v["bytes"] for v in prof.values())
+    kernels = {kk: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
+                    "model_GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else 0.0}
+               for kk, v in prof.items() if v["launches"]}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "colorings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"rmat-s{args.scale}-m{args.edges}-bintree15-k15-{ncol}colorings"),
+            "graph": {"generator": "rmat", "scale": args.scale, "a_b_c": list(gg.RMAT_ABC),
+                      "n": G.n, "nnz": G.nnz, "seed": args.seed},
+            "template": "bintree15", "k": k, "colorings_per_step": ncol,
+            "mode": "fp32 mantissa + per-column exponent, colourings batched",
+        },
+        "fp64_plain": fp64,
+        "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
+        "fp32_vs_fp64_max_rel_err": err,
+        "updates_per_s": (sp["work"] / (sp["ms"] * 1e-3)) if sp["ms"] else None,
+        "hbm_GBps_model_step": total_bytes / (ms_step * 1e-3 * args.steps) / 1e9,
+        "estimate_mean": res32["mean_estimate"],
+        "plan": {"splits": info.n_splits, "spmm_columns": info.spmm_columns,
+                 "pairs_per_vertex": info.pairs_per_vertex, "alpha": info.alpha},
+        "kernels": kernels,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_spmm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": (traffic / (sp["bytes"] / sp["launches"])) if traffic else None,
+            "gather_model_GBps": (sp["work"] * 4 / (sp["ms"] * 1e-3) / 1e9) if sp["ms"] else None,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(parent, k, args.cpu_scale, args.seed, G.n, G.nnz)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -203,6 +203,35 @@ sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph *g,
                              const sg2v_colorings *c, sg2v_mode mode, int32_t which,
                              int32_t node, int32_t kind, void *host_out, void *stream);
 
+/* Kernel timing.  Between sg2v_profile_start and sg2v_profile_stop, every
+ * kernel launch of the library is bracketed by HIP events on the stream it is
+ * launched on.  sg2v_profile_stop synchronises the device and fills out[kind]
+ * for kind = 0 .. SG2V_K_COUNT-1 with the launch count, the summed event time,
+ * and the summed model figures of those launches:
+ *   bytes : compulsory HBM bytes (every table read once and written once,
+ *           the adjacency streamed once per SpMM column chunk);
+ *   work  : SpMM: edge x colour-set updates (nnz x columns);
+ *           eMA/root: multiply-adds (vertices x pairs). */
+#define SG2V_K_COLOR 0
+#define SG2V_K_HIST 1
+#define SG2V_K_SPMM 2
+#define SG2V_K_SPMM_COMBINE 3
+#define SG2V_K_EMA_GENERAL 4
+#define SG2V_K_EMA_SINGLE 5
+#define SG2V_K_ROOT 6
+#define SG2V_K_COUNT 7
+
+typedef struct {
+  int32_t kind;
+  int32_t launches;
+  double ms;
+  double bytes;
+  double work;
+} sg2v_prof_entry_t;
+
+sg2v_status sg2v_profile_start(void);
+sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
+
 /* Tuning knobs (0 = automatic).  spmm_width: columns per SpMM chunk;
  * ema_rows: rows per eMA tile; batch: colourings per pass; budget_bytes:
  * device memory the count may use. */

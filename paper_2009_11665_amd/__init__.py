@@ -65,7 +65,14 @@ EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_des
            "sg2v_plan_info", "sg2v_plan_node", "sg2v_plan_pairs", "sg2v_graph_create", "sg2v_graph_destroy",
            "sg2v_color", "sg2v_colorings_destroy", "sg2v_colorings_download", "sg2v_count",
            "sg2v_count_batch", "sg2v_count_grad", "sg2v_debug_table", "sg2v_set_tuning",
-           "sg2v_get_tuning"]
+           "sg2v_get_tuning", "sg2v_profile_start", "sg2v_profile_stop"]
+
+KERNEL_KINDS = ["color", "hist", "spmm", "spmm_combine", "ema_general", "ema_single", "root"]
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("launches", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("work", ctypes.c_double)]
 
 
 def lib():
@@ -99,6 +106,8 @@ def lib():
         L.sg2v_debug_table.argtypes = [P, P, P, i32, i32, i32, i32, P, P]
         L.sg2v_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.sg2v_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.sg2v_profile_start.argtypes = []
+        L.sg2v_profile_stop.argtypes = [ctypes.POINTER(ProfEntry)]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is ctypes.c_int:  # default restype: status codes
@@ -308,3 +317,16 @@ def get_tuning() -> Tuning:
     t = Tuning()
     _check(lib().sg2v_get_tuning(ctypes.byref(t)), "sg2v_get_tuning")
     return t
+
+
+def profile_start():
+    """Start bracketing every kernel launch with HIP events."""
+    _check(lib().sg2v_profile_start(), "sg2v_profile_start")
+
+
+def profile_stop():
+    """Stop timing; returns {kind: dict(launches, ms, bytes, work)}."""
+    arr = (ProfEntry * len(KERNEL_KINDS))()
+    _check(lib().sg2v_profile_stop(arr), "sg2v_profile_stop")
+    return {KERNEL_KINDS[e.kind]: dict(launches=e.launches, ms=e.ms, bytes=e.bytes, work=e.work)
+            for e in arr}

@@ -92,6 +92,60 @@ sg2v_status upload(const std::vector<T> &h, void **d, hipStream_t s) {
   return SG2V_OK;
 }
 
+// ---------------------------------------------------------------------------
+// kernel timing with HIP events (sg2v_profile_start / sg2v_profile_stop)
+
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  double bytes, work;
+};
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+
+Profiler &profiler() {
+  static Profiler p;
+  return p;
+}
+
+// brackets the kernel launches of its lifetime with events when profiling
+struct ProfScope {
+  bool on;
+  ProfRec r;
+  hipStream_t s;
+  ProfScope(int kind, double bytes, double work, hipStream_t st) : on(profiler().on), s(st) {
+    if (!on) return;
+    r.kind = kind;
+    r.bytes = bytes;
+    r.work = work;
+    std::lock_guard<std::mutex> lk(profiler().mu);
+    r.a = profiler().get();
+    r.b = profiler().get();
+    (void)hipEventRecord(r.a, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(r.b, s);
+    std::lock_guard<std::mutex> lk(profiler().mu);
+    profiler().recs.push_back(r);
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -366,7 +420,11 @@ extern "C" sg2v_status sg2v_color(const sg2v_graph *g, int32_t k, uint64_t seed,
   c->first = first;
   c->seed = seed;
   HIP_TRY(hipMalloc((void **)&c->d, g->n * n_colorings));
-  launch_color(c->d, g->n, k, seed, first, n_colorings, (hipStream_t)stream);
+  {
+    ProfScope ps(SG2V_K_COLOR, (double)g->n * n_colorings, (double)g->n * n_colorings,
+                 (hipStream_t)stream);
+    launch_color(c->d, g->n, k, seed, first, n_colorings, (hipStream_t)stream);
+  }
   HIP_TRY(hipGetLastError());
   *out = c.release();
   return SG2V_OK;
@@ -396,17 +454,21 @@ struct DevPlan {
 };
 
 // device copies of a plan's tables, one per device, kept with the plan
+void fill_devplan(const Plan::DeviceTables &d, DevPlan *out) {
+  out->pairs.assign(d.pairs.size(), nullptr);
+  out->drop.assign(d.drop.size(), nullptr);
+  for (size_t i = 0; i < d.pairs.size(); ++i) {
+    out->pairs[i] = (int32_t *)d.pairs[i];
+    out->drop[i] = (int32_t *)d.drop[i];
+  }
+  out->root_list = (int32_t *)d.root_list;
+}
+
 sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) {
   std::lock_guard<std::mutex> lk(P.mu);
   for (auto &d : P.dev)
     if (d.device == device) {
-      out->pairs.assign(d.pairs.size(), nullptr);
-      out->drop.assign(d.drop.size(), nullptr);
-      for (size_t i = 0; i < d.pairs.size(); ++i) {
-        out->pairs[i] = (int32_t *)d.pairs[i];
-        out->drop[i] = (int32_t *)d.drop[i];
-      }
-      out->root_list = (int32_t *)d.root_list;
+      fill_devplan(d, out);
       return SG2V_OK;
     }
   Plan::DeviceTables D;
@@ -430,7 +492,8 @@ sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) 
   if (!P.root_list.empty()) ST_TRY(upload(P.root_list, &D.root_list, s));
   HIP_TRY(hipStreamSynchronize(s));
   P.dev.push_back(D);
-  return plan_device(P, device, s, out);
+  fill_devplan(P.dev.back(), out);
+  return SG2V_OK;
 }
 
 enum StepKind { S_HIST, S_SPMM, S_EMA_SINGLE, S_EMA_GENERAL, S_ROOT };
@@ -645,7 +708,13 @@ sg2v_status step_hist(Ctx &x, int node) {
   a.H = H.p;
   a.ldh = H.ld;
   const int64_t blocks = std::min<int64_t>((x.g->n + 3) / 4, 4096);
-  launch_hist(x.dt, a, (int)std::max<int64_t>(blocks, 1), x.s);
+  {
+    const double nnz = (double)x.g->nnz;
+    ProfScope ps(SG2V_K_HIST,
+                 nnz * (4.0 + (x.g->w ? 4.0 : 0.0) + x.b) + (double)x.g->n * (8.0 + x.b * x.P->k * x.es),
+                 nnz * x.b, x.s);
+    launch_hist(x.dt, a, (int)std::max<int64_t>(blocks, 1), x.s);
+  }
   if (x.dt == DT_U64) launch_zero_pad(x.dt, H.p, x.g->n, H.ld, H.cols * x.b, x.s);
   if (x.dt == DT_F32) {
     const int64_t nc = H.cols * x.b;
@@ -690,9 +759,15 @@ sg2v_status step_spmm(Ctx &x, int node) {
   const int64_t chunks = (nc + W - 1) / W;
   dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
             (unsigned)chunks);
-  if (launch_spmm(x.dt, a, x.pp.G, grid, x.s)) {
-    set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
-    return SG2V_EINVAL;
+  {
+    const double n = (double)x.g->n, nnz = (double)x.g->nnz;
+    const double bytes = 2.0 * n * (double)nc * x.es +
+                         (double)chunks * (nnz * (4.0 + (x.g->w ? 4.0 : 0.0)) + 20.0 * x.g->n_tasks);
+    ProfScope ps(SG2V_K_SPMM, bytes, nnz * (double)nc, x.s);
+    if (launch_spmm(x.dt, a, x.pp.G, grid, x.s)) {
+      set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
+      return SG2V_EINVAL;
+    }
   }
   CombineArgs cb;
   cb.partial = a.partial;
@@ -705,7 +780,11 @@ sg2v_status step_spmm(Ctx &x, int node) {
   cb.n_long = x.g->n_long;
   cb.mx = a.mx;
   cb.ovf = x.ovf;
-  launch_spmm_combine(x.dt, cb, x.s);
+  if (x.g->n_long > 0) {
+    ProfScope ps(SG2V_K_SPMM_COMBINE, (double)(x.g->n_slots + x.g->n_long) * nc * x.es,
+                 (double)x.g->n_slots * nc, x.s);
+    launch_spmm_combine(x.dt, cb, x.s);
+  }
   if (x.dt == DT_F32) {
     launch_copy_i32(Mp.e, B.e, nc, x.s);
     norm(x, B);
@@ -751,6 +830,8 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
     const int64_t rpi = cpad >= 256 ? 1 : 256 / cpad;
     dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((x.g->n + rpi - 1) / rpi, 4096)),
               (unsigned)x.b);
+    ProfScope ps(SG2V_K_EMA_SINGLE, (double)x.g->n * x.b * (double)(nd.cols + Bt.cols) * x.es,
+                 (double)x.g->n * x.b * (double)nd.cols, x.s);
     launch_ema_single(x.dt, a, grid, lmx, x.s);
   } else {
     Tab &Ma = x.pp.M[nd.active];
@@ -774,6 +855,9 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
     const int64_t per_cu = std::max<int64_t>(1, (int64_t)(x.lds_max / std::max<size_t>(lds, 1)));
     const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8));
     dim3 grid((unsigned)std::max<int64_t>(blocks, 1), (unsigned)x.b);
+    ProfScope ps(SG2V_K_EMA_GENERAL,
+                 (double)x.g->n * x.b * (double)(nd.cols + Ma.cols + Bt.cols) * x.es,
+                 (double)x.g->n * x.b * (double)nd.cols * nd.np, x.s);
     if (launch_ema_general(x.dt, a, R, stage, grid, lds, x.s)) {
       set_error("sg2v_count: no eMA variant for R=%d", R);
       return SG2V_EINVAL;
@@ -828,7 +912,12 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const int nblk = 1024;
   a.partial = x.ws->partial.p;
   a.ovf = x.ovf;
-  launch_root(x.dt, a, dim3(nblk, x.b), x.s);
+  {
+    ProfScope ps(SG2V_K_ROOT,
+                 (double)x.g->n * x.b * (double)(X->cols + (Y ? Y->cols : 0)) * x.es,
+                 (double)x.g->n * x.b * (double)P.root_L, x.s);
+    launch_root(x.dt, a, dim3(nblk, x.b), x.s);
+  }
   const int es = 8;
   launch_root_final(x.dt, a.partial, nblk, x.b, (char *)result + (size_t)x.j0 * es, x.ovf, x.s);
   if (x.dt == DT_F32) launch_root_exp(X->E, Y ? Y->E : nullptr, Eout + x.j0, x.b, x.s);
@@ -1122,4 +1211,45 @@ extern "C" void sg2v_plan_destroy(sg2v_plan *plan) {
     (void)hipSetDevice(cur);
   }
   delete plan;
+}
+
+extern "C" sg2v_status sg2v_profile_start(void) {
+  Profiler &p = profiler();
+  std::lock_guard<std::mutex> lk(p.mu);
+  for (auto &r : p.recs) {
+    p.pool.push_back(r.a);
+    p.pool.push_back(r.b);
+  }
+  p.recs.clear();
+  p.on = true;
+  return SG2V_OK;
+}
+
+extern "C" sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out) {
+  if (!out) {
+    set_error("sg2v_profile_stop: null");
+    return SG2V_EINVAL;
+  }
+  Profiler &p = profiler();
+  std::lock_guard<std::mutex> lk(p.mu);
+  p.on = false;
+  for (int k = 0; k < SG2V_K_COUNT; ++k) {
+    out[k].kind = k;
+    out[k].launches = 0;
+    out[k].ms = out[k].bytes = out[k].work = 0.0;
+  }
+  for (auto &r : p.recs) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    sg2v_prof_entry_t &e = out[r.kind];
+    e.launches++;
+    e.ms += ms;
+    e.bytes += r.bytes;
+    e.work += r.work;
+    p.pool.push_back(r.a);
+    p.pool.push_back(r.b);
+  }
+  p.recs.clear();
+  return SG2V_OK;
 }
