@@ -175,7 +175,7 @@ def main():
     err = None
     if not args.no_fp64:
         old = sg.get_tuning()
-        sg.set_tuning(old.spmm_width, old.ema_rows, 1, old.budget_bytes)
+        sg.set_tuning(old.spmm_width, old.ema_rows, 1, old.budget_bytes, old.flags)
         try:
             torch.cuda.synchronize()
             t2 = time.perf_counter()
@@ -185,7 +185,7 @@ def main():
             torch.cuda.synchronize()
             t3 = time.perf_counter()
         finally:
-            sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes)
+            sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
         fp64 = {"value": ncol * args.fp64_steps / (t3 - t2), "unit": "colorings/s",
                 "ms_per_step": (t3 - t2) / args.fp64_steps * 1e3}
         err = max(abs(a - b) / abs(b) for a, b in zip(res32["colorful"], r64["colorful"]) if b)

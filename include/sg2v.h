@@ -233,13 +233,15 @@ sg2v_status sg2v_profile_start(void);
 sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
 
 /* Tuning knobs (0 = automatic).  spmm_width: columns per SpMM chunk;
- * ema_rows: rows per eMA tile; batch: colourings per pass; budget_bytes:
- * device memory the count may use. */
+ * ema_rows: rows per eMA tile; batch: colourings per pass; flags:
+ * SG2V_TUNE_NO_COLOR_SKIP disables the colour-based skipping of SpMM row
+ * segments; budget_bytes: device memory the count may use. */
+#define SG2V_TUNE_NO_COLOR_SKIP 1
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;
   int32_t batch;
-  int32_t reserved;
+  int32_t flags;
   int64_t budget_bytes;
 } sg2v_tuning_t;
 

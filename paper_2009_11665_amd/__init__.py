@@ -57,7 +57,7 @@ class NodeInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("spmm_width", ctypes.c_int32), ("ema_rows", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("budget_bytes", ctypes.c_int64)]
 
 
@@ -308,8 +308,12 @@ def count_grad(plan: Plan, graph: Graph, col: Colorings, grad_colorful, mode="fp
     return out
 
 
-def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0):
-    t = Tuning(spmm_width, ema_rows, batch, 0, budget_bytes)
+TUNE_NO_COLOR_SKIP = 1
+
+
+def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,
+               flags: int = 0):
+    t = Tuning(spmm_width, ema_rows, batch, flags, budget_bytes)
     _check(lib().sg2v_set_tuning(ctypes.byref(t)), "sg2v_set_tuning")
 
 
@@ -330,3 +334,40 @@ def profile_stop():
     _check(lib().sg2v_profile_stop(arr), "sg2v_profile_stop")
     return {KERNEL_KINDS[e.kind]: dict(launches=e.launches, ms=e.ms, bytes=e.bytes, work=e.work)
             for e in arr}
+
+
+class SubgraphCount:
+    """Differentiable colourful count: ``SubgraphCount.apply(w, plan, row_ptr,
+    col_idx, seed, n_colorings)`` returns the colourful count of each colouring
+    (float64 [n_colorings]) of the graph whose CSR entries carry the weights
+    ``w`` (device tensor [nnz]); its backward gives d/dw per directed entry via
+    sg2v_count_grad (FP64).  The forward runs in FP64 as well."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, w, plan, row_ptr, col_idx, seed, n_colorings):
+        if cls._fn is None:
+            import torch
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, w, plan, row_ptr, col_idx, seed, n_colorings):
+                    n = row_ptr.numel() - 1
+                    g = Graph(n, row_ptr, col_idx, w.detach())
+                    c = Colorings(g, plan.k, seed, n_colorings)
+                    r = count(plan, g, c, "fp64")
+                    ctx.keep = (g, c, plan)
+                    return torch.as_tensor(r["colorful"], dtype=torch.float64, device=w.device)
+
+                @staticmethod
+                def backward(ctx, grad_out):
+                    g, c, plan = ctx.keep
+                    gw = count_grad(plan, g, c, grad_out.detach().double().cpu().numpy(), "fp64")
+                    return gw.to(w_dtype(ctx)), None, None, None, None, None
+
+            def w_dtype(ctx):
+                return ctx.keep[0]._keep[2].dtype
+
+            cls._fn = _F
+        return cls._fn.apply(w, plan, row_ptr, col_idx, seed, n_colorings)

@@ -3,7 +3,9 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -38,6 +40,12 @@ struct Node {
   int np = 0;                  // pairs per output column = C(size, size_a)
   std::vector<int32_t> pairs;  // [cols][np] x (ia, ip)
   std::vector<int32_t> drop;   // active child is one vertex: [k][cols] -> rank(C\{c}) or -1
+  // adjoint tables (reverse-mode derivative of the multiply-add):
+  int np_ta = 0;               // pairs per active column = C(k - size_a, size_p)
+  std::vector<int32_t> tr_a;   // [cols_a][np_ta] x (I_s, I_p): output sets containing I_a
+  int np_tp = 0;               // pairs per passive column = C(k - size_p, size_a)
+  std::vector<int32_t> tr_p;   // [cols_p][np_tp] x (I_s, I_a): output sets containing I_p
+  std::vector<int32_t> add;    // active child is one vertex: [k][cols_p] -> rank(P + {c}) or -1
 };
 
 enum RootKind {
@@ -69,7 +77,10 @@ struct Plan {
   struct DeviceTables {
     int device = -1;
     std::vector<void *> pairs, drop;  // per node
+    std::vector<void *> tr_a, tr_p, add;
     void *root_list = nullptr;
+    // SpMM colour-skip masks per (node, colourings per pass, chunk width)
+    std::map<std::tuple<int, int, int>, void *> chunks;
   };
   mutable std::mutex mu;
   mutable std::vector<DeviceTables> dev;

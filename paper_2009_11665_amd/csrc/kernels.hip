@@ -107,6 +107,11 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
   const int wv = threadIdx.x / WAVE;
   const int sub = lane % G;
   const int64_t col0 = (int64_t)blockIdx.y * W + sub * N;
+  // colour skipping for this chunk
+  const int jb = a.chunk_jb ? a.chunk_jb[blockIdx.y] : -1;
+  const uint8_t *colj = jb >= 0 ? a.colors + (int64_t)(a.j0 + jb) * a.n : nullptr;
+  const uint32_t umask = jb >= 0 ? a.chunk_union[blockIdx.y] : 0xFFFFFFFFu;
+  const uint32_t imask = jb >= 0 ? a.chunk_inter[blockIdx.y] : 0u;
   const T *__restrict__ M = (const T *)a.M;
   T *__restrict__ B = (T *)a.B;
   T *__restrict__ Pt = (T *)a.partial;
@@ -133,7 +138,10 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       beg = a.task_beg[t];
       len = a.task_len[t];
       slot = a.task_slot[t];
+      if (colj && (imask >> colj[row] & 1u)) len = 0;  // row never read here: zeros
     }
+    const uint64_t gmask = (lpt == 64) ? ~0ull : (((1ull << lpt) - 1ull) << gbase);
+    const uint64_t lt = (1ull << lane) - 1ull;
     V16<T> acc0, acc1, acc2, acc3;
 #pragma unroll
     for (int u = 0; u < N; ++u) acc0.x[u] = acc1.x[u] = acc2.x[u] = acc3.x[u] = T(0);
@@ -142,11 +150,24 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       const int e = base + tl;
       int my_j = 0;
       float my_w = 1.0f;
+      bool keep = false;
       if (e < len) {
         my_j = a.col_idx[beg + e];
         if constexpr (WEIGHTED) my_w = a.w[beg + e];
+        keep = colj ? ((umask >> colj[my_j]) & 1u) != 0 : true;
       }
-      const int cnt = min(lpt, len - base);
+      // compact the kept neighbours to the first lanes of the task's group,
+      // preserving their order (a permutation of the group's lanes)
+      int cnt;
+      {
+        const uint64_t km = __ballot(keep) & gmask;
+        const uint64_t dm = ~km & gmask;
+        cnt = __popcll(km);
+        const int dst = keep ? gbase + __popcll(km & lt) : gbase + cnt + __popcll(dm & lt);
+        my_j = __builtin_amdgcn_ds_permute(dst << 2, my_j);
+        if constexpr (WEIGHTED)
+          my_w = __builtin_bit_cast(float, __builtin_amdgcn_ds_permute(dst << 2, __builtin_bit_cast(int, my_w)));
+      }
       int s = stream;
       for (; s + 3 * streams < cnt; s += 4 * streams) {
         const int j0 = shfl_i32(my_j, gbase + s);
@@ -200,6 +221,11 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
     }
     if (valid && stream == 0) {
       if (slot < 0) {
+        if (a.accumulate) {
+          const V16<T> old = *(const V16<T> *)(B + (int64_t)row * a.ldb + col0);
+#pragma unroll
+          for (int u = 0; u < N; ++u) acc0.x[u] = A::add(acc0.x[u], old.x[u], ovf);
+        }
         *(V16<T> *)(B + (int64_t)row * a.ldb + col0) = acc0;
 #pragma unroll
         for (int u = 0; u < N; ++u)
@@ -260,6 +286,11 @@ __global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
       const V16<T> v = *(const V16<T> *)(P + (int64_t)(s0 + s) * a.ld + c0);
 #pragma unroll
       for (int u = 0; u < N; ++u) acc.x[u] = A::add(acc.x[u], v.x[u], ovf);
+    }
+    if (a.accumulate) {
+      const V16<T> old = *(const V16<T> *)(B + (int64_t)row * a.ld + c0);
+#pragma unroll
+      for (int u = 0; u < N; ++u) acc.x[u] = A::add(acc.x[u], old.x[u], ovf);
     }
     *(V16<T> *)(B + (int64_t)row * a.ld + c0) = acc;
 #pragma unroll
@@ -366,6 +397,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
       for (int r = 0; r < R; ++r) {
         const int64_t row = r0 + r;
         if (row < a.n) {
+          if (a.accumulate) acc[r] = A::add(acc[r], Ms[row * a.lds + (int64_t)j * a.Cs + C], ovf);
           Ms[row * a.lds + (int64_t)j * a.Cs + C] = acc[r];
           if constexpr (SCALED) m = fmaxf(m, (float)acc[r]);
         }
@@ -574,6 +606,53 @@ __global__ void k_zero_pad(T *X, int64_t n, int64_t ld, int64_t c_from) {
 }
 
 // ===========================================================================
+// Edge gradient of the neighbour aggregation (the adjoint of B = A_G M_p with
+// respect to the CSR weights): grad[e] += sum_c Bbar(i, c) M_p(j, c) for
+// e = (i -> j).  One wave per row, four neighbours at a time with 16 lanes
+// each; every entry is owned by one lane, so no atomics.  With a one-vertex
+// passive child M_p(j, .) is the colour indicator and the sum is
+// sum_jj Bbar(i, jj*k + colour_jj(j)).
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_sddmm(SddmmArgs a) {
+  using A = Arith<T>;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int grp = lane >> 4, sub = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+  const T *Bb = (const T *)a.Bbar;
+  const T *M = (const T *)a.Mp;
+  bool ovf = false;
+  for (int64_t i = wave; i < a.n; i += nwaves) {
+    const int64_t beg = a.row_ptr[i], end = a.row_ptr[i + 1];
+    const T *brow = Bb + i * a.ldb;
+    for (int64_t e0 = beg; e0 < end; e0 += 4) {
+      const int64_t e = e0 + grp;
+      T s = T(0);
+      if (e < end) {
+        const int64_t j = a.col_idx[e];
+        if (M) {
+          const T *mrow = M + j * a.ldm;
+          for (int64_t c = sub; c < a.ncols; c += 16) s = A::fma(brow[c], mrow[c], s, ovf);
+        } else {
+          for (int jj = sub; jj < a.b; jj += 16)
+            s = A::add(s, brow[(int64_t)jj * a.k + a.colors[(int64_t)(a.j0 + jj) * a.n + j]], ovf);
+        }
+      }
+      for (int off = 1; off < 16; off <<= 1) s = A::add(s, shfl_xor(s, off), ovf);
+      if (e < end && sub == 0) a.grad[e] += (double)s;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_fill_value(T *X, int64_t count, T v) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count;
+       x += (int64_t)gridDim.x * blockDim.x)
+    X[x] = v;
+}
+
+// ===========================================================================
 // launchers
 
 static inline unsigned grid_cap(int64_t want, int64_t cap) {
@@ -708,6 +787,20 @@ void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
 void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_copy_i32<<<grid_cap((n + BLOCK - 1) / BLOCK, 4096), BLOCK, 0, s>>>(src, dst, n);
+}
+
+void launch_sddmm(int dtype, const SddmmArgs &a, hipStream_t s) {
+  const unsigned g = grid_cap((a.n + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 4096);
+  if (dtype == DT_F64) k_sddmm<double><<<g, BLOCK, 0, s>>>(a);
+  else if (dtype == DT_F32) k_sddmm<float><<<g, BLOCK, 0, s>>>(a);
+}
+
+void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return;
+  const unsigned g = grid_cap((count + BLOCK - 1) / BLOCK, 65536);
+  if (dtype == DT_F64) k_fill_value<double><<<g, BLOCK, 0, s>>>((double *)X, count, v);
+  else if (dtype == DT_F32) k_fill_value<float><<<g, BLOCK, 0, s>>>((float *)X, count, (float)v);
+  else k_fill_value<uint64_t><<<g, BLOCK, 0, s>>>((uint64_t *)X, count, (uint64_t)v);
 }
 
 void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, hipStream_t s) {

@@ -40,6 +40,18 @@ struct SpmmArgs {
   int64_t ncols_valid;
   unsigned *mx;            // FP32S column maxima (nullable)
   int *ovf;
+  int32_t accumulate;      // 1: B += A M (adjoint), 0: B = A M
+  // colour skipping (nullable): per chunk, the colouring block it lies in
+  // (-1: spans blocks, no skipping), the union and the intersection of its
+  // colour sets.  A neighbour j whose colour is outside the union has a zero
+  // row segment; a row i whose colour is in the intersection is never read
+  // through this chunk (written as zeros).
+  const int32_t *chunk_jb;
+  const uint32_t *chunk_union;
+  const uint32_t *chunk_inter;
+  const uint8_t *colors;
+  int32_t j0;
+  int64_t n;
 };
 
 struct CombineArgs {
@@ -53,6 +65,7 @@ struct CombineArgs {
   int32_t n_long;
   unsigned *mx;
   int *ovf;
+  int32_t accumulate;
 };
 
 struct EmaArgs {
@@ -73,6 +86,22 @@ struct EmaArgs {
   unsigned *mx;          // FP32S output column maxima
   int *es;               // FP32S output column exponents
   int *ovf;
+  int32_t accumulate;    // general kernel: 1 adds into Ms (adjoint)
+};
+
+// edge gradient: grad[e] += sum_c Bbar(i, c) * M_p(j, c) for e = (i -> j)
+struct SddmmArgs {
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const void *Bbar;
+  int64_t ldb;
+  const void *Mp;  // null: one-vertex passive child (one-hot by colour)
+  int64_t ldm;
+  int64_t ncols;   // b * C(k, |T_p|)
+  int64_t n;
+  const uint8_t *colors;
+  int32_t j0, b, k;
+  double *grad;
 };
 
 struct RootArgs {
@@ -109,6 +138,8 @@ void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, 
 void launch_root_exp(const int *EX, const int *EY, int *out, int b, hipStream_t s);
 void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s);
+void launch_sddmm(int dtype, const SddmmArgs &a, hipStream_t s);
+void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t s);
 void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, hipStream_t s);
 
 }  // namespace sg2v

@@ -266,6 +266,39 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
     }
   }
 
+  // Adjoint tables: the same splits grouped by the active set and by the
+  // passive set, and the one-vertex-active inverse (P -> P + {c}).
+  for (auto &nd : P->nodes) {
+    if (nd.size == 1) continue;
+    const Node &A = P->nodes[nd.active];
+    const Node &Pn = P->nodes[nd.passive];
+    const int64_t ca = binom(k, A.size), cp = binom(k, Pn.size);
+    nd.np_ta = (int)binom(k - A.size, Pn.size);
+    nd.np_tp = (int)binom(k - Pn.size, A.size);
+    nd.tr_a.assign((size_t)ca * nd.np_ta * 2, -1);
+    nd.tr_p.assign((size_t)cp * nd.np_tp * 2, -1);
+    std::vector<int> fa(ca, 0), fp(cp, 0);
+    for (int64_t r = 0; r < nd.cols; ++r)
+      for (int q = 0; q < nd.np; ++q) {
+        const int32_t ia = nd.pairs[((size_t)r * nd.np + q) * 2 + 0];
+        const int32_t ip = nd.pairs[((size_t)r * nd.np + q) * 2 + 1];
+        const size_t xa = ((size_t)ia * nd.np_ta + fa[ia]++) * 2;
+        nd.tr_a[xa] = (int32_t)r;
+        nd.tr_a[xa + 1] = ip;
+        const size_t xp = ((size_t)ip * nd.np_tp + fp[ip]++) * 2;
+        nd.tr_p[xp] = (int32_t)r;
+        nd.tr_p[xp + 1] = ia;
+      }
+    if (A.size == 1) {
+      nd.add.assign((size_t)k * cp, -1);
+      for (int64_t r = 0; r < cp; ++r) {
+        const uint32_t Pm = colex_unrank(r, Pn.size, k);
+        for (int c = 0; c < k; ++c)
+          if (!(Pm >> c & 1u)) nd.add[(size_t)c * cp + r] = (int32_t)colex_rank(Pm | (1u << c));
+      }
+    }
+  }
+
   // Root reduction lists.
   P->fused.assign(P->nodes.size(), 0);
   const Node &R = P->nodes[P->root];

@@ -450,16 +450,35 @@ namespace {
 
 struct DevPlan {
   std::vector<int32_t *> pairs, drop;  // per node, device
+  std::vector<int32_t *> tr_a, tr_p, add;
   int32_t *root_list = nullptr;
 };
 
+// pair-major copy ([q][col]) of a [col][np] x 2 table
+std::vector<int32_t> pair_major(const std::vector<int32_t> &t, int64_t cols, int np) {
+  std::vector<int32_t> o(t.size());
+  for (int64_t C = 0; C < cols; ++C)
+    for (int q = 0; q < np; ++q) {
+      o[((size_t)q * cols + C) * 2 + 0] = t[((size_t)C * np + q) * 2 + 0];
+      o[((size_t)q * cols + C) * 2 + 1] = t[((size_t)C * np + q) * 2 + 1];
+    }
+  return o;
+}
+
 // device copies of a plan's tables, one per device, kept with the plan
 void fill_devplan(const Plan::DeviceTables &d, DevPlan *out) {
-  out->pairs.assign(d.pairs.size(), nullptr);
-  out->drop.assign(d.drop.size(), nullptr);
-  for (size_t i = 0; i < d.pairs.size(); ++i) {
+  const size_t nn = d.pairs.size();
+  out->pairs.assign(nn, nullptr);
+  out->drop.assign(nn, nullptr);
+  out->tr_a.assign(nn, nullptr);
+  out->tr_p.assign(nn, nullptr);
+  out->add.assign(nn, nullptr);
+  for (size_t i = 0; i < nn; ++i) {
     out->pairs[i] = (int32_t *)d.pairs[i];
     out->drop[i] = (int32_t *)d.drop[i];
+    out->tr_a[i] = (int32_t *)d.tr_a[i];
+    out->tr_p[i] = (int32_t *)d.tr_p[i];
+    out->add[i] = (int32_t *)d.add[i];
   }
   out->root_list = (int32_t *)d.root_list;
 }
@@ -473,21 +492,23 @@ sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) 
     }
   Plan::DeviceTables D;
   D.device = device;
-  D.pairs.assign(P.nodes.size(), nullptr);
-  D.drop.assign(P.nodes.size(), nullptr);
-  for (size_t i = 0; i < P.nodes.size(); ++i) {
+  const size_t nn = P.nodes.size();
+  D.pairs.assign(nn, nullptr);
+  D.drop.assign(nn, nullptr);
+  D.tr_a.assign(nn, nullptr);
+  D.tr_p.assign(nn, nullptr);
+  D.add.assign(nn, nullptr);
+  for (size_t i = 0; i < nn; ++i) {
     const Node &nd = P.nodes[i];
     if (nd.size > 1) {
-      // transpose pairs to [q][C] so that consecutive columns are contiguous
-      std::vector<int32_t> t((size_t)nd.cols * nd.np * 2);
-      for (int64_t C = 0; C < nd.cols; ++C)
-        for (int q = 0; q < nd.np; ++q) {
-          t[((size_t)q * nd.cols + C) * 2 + 0] = nd.pairs[((size_t)C * nd.np + q) * 2 + 0];
-          t[((size_t)q * nd.cols + C) * 2 + 1] = nd.pairs[((size_t)C * nd.np + q) * 2 + 1];
-        }
-      ST_TRY(upload(t, &D.pairs[i], s));
+      // pair-major ([q][C]) so that consecutive columns are contiguous
+      ST_TRY(upload(pair_major(nd.pairs, nd.cols, nd.np), &D.pairs[i], s));
+      const int64_t ca = P.nodes[nd.active].cols, cp = P.nodes[nd.passive].cols;
+      ST_TRY(upload(pair_major(nd.tr_a, ca, nd.np_ta), &D.tr_a[i], s));
+      ST_TRY(upload(pair_major(nd.tr_p, cp, nd.np_tp), &D.tr_p[i], s));
     }
     if (!nd.drop.empty()) ST_TRY(upload(nd.drop, &D.drop[i], s));
+    if (!nd.add.empty()) ST_TRY(upload(nd.add, &D.add[i], s));
   }
   if (!P.root_list.empty()) ST_TRY(upload(P.root_list, &D.root_list, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -529,7 +550,7 @@ struct PassPlan {
 };
 
 struct Workspace {
-  DevBuf arena, small, partial, result, ovf;
+  DevBuf arena, small, partial, result, ovf, grad;
 };
 
 Workspace &workspace() {
@@ -553,9 +574,14 @@ int pick_G(int dt, int64_t widest_cols_b) {
   return p2;
 }
 
+struct PassOpts {
+  std::vector<std::pair<int, int>> keep;  // (node, 0: M / 1: B) kept to the end of the pass
+  bool no_fuse = false;                   // materialise every non-root table
+};
+
 // Build the step list and table lifetimes for a pass over b colourings.
 void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots, PassPlan &pp,
-                int debug_node, int debug_kind) {
+                const PassOpts &opt) {
   const int es = esize_of(dt);
   const int N = dt == DT_F32 ? 4 : 2;
   const int64_t align = std::max<int64_t>(128 / es, (int64_t)G * N);
@@ -580,7 +606,9 @@ void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots,
       pp.steps.push_back({S_ROOT, (int)s});
       continue;
     }
-    if (P.fused[s] && (int)s != debug_node) continue;
+    bool kept = false;
+    for (auto &kp : opt.keep) kept |= kp.first == (int)s && kp.second == 0;
+    if (P.fused[s] && !opt.no_fuse && !kept) continue;
     needB(nd.passive);
     pp.steps.push_back({P.nodes[nd.active].size == 1 ? S_EMA_SINGLE : S_EMA_GENERAL, (int)s});
   }
@@ -606,9 +634,9 @@ void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots,
         break;
     }
   }
-  if (debug_node >= 0) {
-    Tab &t = debug_kind == 0 ? pp.M[debug_node] : pp.B[debug_node];
-    t.last = (int)pp.steps.size();
+  for (auto &kp : opt.keep) {
+    Tab &t = kp.second == 0 ? pp.M[kp.first] : pp.B[kp.first];
+    if (t.last >= 0) t.last = (int)pp.steps.size();
   }
   // sizes
   std::vector<Tab *> all;
@@ -728,6 +756,52 @@ sg2v_status step_hist(Ctx &x, int node) {
   return SG2V_OK;
 }
 
+// Per chunk of W columns of a passive node's table (b colourings side by
+// side): the colouring block holding the whole chunk (-1 if it spans two
+// blocks or padding), and the union and intersection of its colour sets.
+sg2v_status chunk_masks(Ctx &x, int node, int W, const int32_t **jb, const uint32_t **un,
+                        const uint32_t **in) {
+  const Plan &P = *x.P;
+  std::lock_guard<std::mutex> lk(P.mu);
+  Plan::DeviceTables *D = nullptr;
+  for (auto &d : P.dev)
+    if (d.device == x.g->device) D = &d;
+  if (!D) {
+    set_error("sg2v_count: plan tables missing on device %d", x.g->device);
+    return SG2V_EINVAL;
+  }
+  const Node &nd = P.nodes[node];
+  const int64_t C = nd.cols, nc = C * x.b, nch = (nc + W - 1) / W;
+  auto key = std::make_tuple(node, x.b, W);
+  auto it = D->chunks.find(key);
+  if (it == D->chunks.end()) {
+    std::vector<uint32_t> h((size_t)nch * 3);
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      const int64_t c0 = ch * W, c1 = std::min<int64_t>(c0 + W, nc);
+      const int64_t b0 = c0 / C, b1 = (c1 - 1) / C;
+      uint32_t u = 0, i = ~0u;
+      for (int64_t c = c0; c < c1; ++c) {
+        const uint32_t m = colex_unrank(c % C, nd.size, P.k);
+        u |= m;
+        i &= m;
+      }
+      const bool one = b0 == b1 && c1 - c0 == W;
+      h[ch] = one ? (uint32_t)b0 : 0xFFFFFFFFu;
+      h[nch + ch] = u;
+      h[2 * nch + ch] = i;
+    }
+    void *d = nullptr;
+    ST_TRY(upload(h, &d, x.s));
+    HIP_TRY(hipStreamSynchronize(x.s));
+    it = D->chunks.emplace(key, d).first;
+  }
+  const uint32_t *base = (const uint32_t *)it->second;
+  *jb = (const int32_t *)base;
+  *un = base + nch;
+  *in = base + 2 * nch;
+  return SG2V_OK;
+}
+
 sg2v_status step_spmm(Ctx &x, int node) {
   Tab &Mp = x.pp.M[node];
   Tab &B = x.pp.B[node];
@@ -755,6 +829,14 @@ sg2v_status step_spmm(Ctx &x, int node) {
   a.ncols_valid = nc;
   a.mx = x.dt == DT_F32 ? B.mx : nullptr;
   a.ovf = x.ovf;
+  a.accumulate = 0;
+  a.chunk_jb = nullptr;
+  a.chunk_union = a.chunk_inter = nullptr;
+  a.colors = x.c->d;
+  a.j0 = x.j0;
+  a.n = x.g->n;
+  if (!(tuning().flags & SG2V_TUNE_NO_COLOR_SKIP))
+    ST_TRY(chunk_masks(x, node, W, &a.chunk_jb, &a.chunk_union, &a.chunk_inter));
   if (x.dt == DT_F32) launch_fill_u32(B.mx, nc, 0u, x.s);
   const int64_t chunks = (nc + W - 1) / W;
   dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
@@ -780,6 +862,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
   cb.n_long = x.g->n_long;
   cb.mx = a.mx;
   cb.ovf = x.ovf;
+  cb.accumulate = 0;
   if (x.g->n_long > 0) {
     ProfScope ps(SG2V_K_SPMM_COMBINE, (double)(x.g->n_slots + x.g->n_long) * nc * x.es,
                  (double)x.g->n_slots * nc, x.s);
@@ -788,6 +871,32 @@ sg2v_status step_spmm(Ctx &x, int node) {
   if (x.dt == DT_F32) {
     launch_copy_i32(Mp.e, B.e, nc, x.s);
     norm(x, B);
+  }
+  return SG2V_OK;
+}
+
+// Multiply-add over pairs (Alg. 3 stage 2) with rows staged in LDS when they
+// fit: picks the rows per tile and the grid, then launches k_ema_general.
+sg2v_status launch_general(Ctx &x, EmaArgs &a) {
+  const bool sc = x.dt == DT_F32;
+  const size_t lmx = sc ? (size_t)a.Cs * 4 : 0;
+  sg2v_tuning_t tu = tuning();
+  const size_t budget = std::min<size_t>(x.lds_max, 64 * 1024);
+  const size_t rowb = (size_t)((a.Ca | 1) + (a.Cb | 1)) * x.es;
+  int R = 16;
+  if (tu.ema_rows > 0) R = tu.ema_rows;
+  while (R > 1 && R * rowb + lmx > budget) R /= 2;
+  const bool stage = R * rowb + lmx <= budget;
+  if (!stage) R = 4;
+  const size_t lds = (stage ? R * rowb : 0) + lmx;
+  const int64_t ntiles = (x.g->n + R - 1) / R;
+  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(x.lds_max / std::max<size_t>(lds, 1)));
+  const int64_t blocks =
+      std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8));
+  dim3 grid((unsigned)std::max<int64_t>(blocks, 1), (unsigned)x.b);
+  if (launch_ema_general(x.dt, a, R, stage, grid, lds, x.s)) {
+    set_error("sg2v_count: no eMA variant for R=%d", R);
+    return SG2V_EINVAL;
   }
   return SG2V_OK;
 }
@@ -842,26 +951,10 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
       a.fa = Ma.f;
       a.Ea = Ma.E;
     }
-    sg2v_tuning_t tu = tuning();
-    const size_t budget = std::min<size_t>(x.lds_max, 64 * 1024);
-    const size_t rowb = (size_t)((a.Ca | 1) + (a.Cb | 1)) * x.es;
-    int R = 16;
-    if (tu.ema_rows > 0) R = tu.ema_rows;
-    while (R > 1 && R * rowb + lmx > budget) R /= 2;
-    bool stage = R * rowb + lmx <= budget;
-    if (!stage) R = 4;
-    const size_t lds = (stage ? R * rowb : 0) + lmx;
-    const int64_t ntiles = (x.g->n + R - 1) / R;
-    const int64_t per_cu = std::max<int64_t>(1, (int64_t)(x.lds_max / std::max<size_t>(lds, 1)));
-    const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8));
-    dim3 grid((unsigned)std::max<int64_t>(blocks, 1), (unsigned)x.b);
     ProfScope ps(SG2V_K_EMA_GENERAL,
                  (double)x.g->n * x.b * (double)(nd.cols + Ma.cols + Bt.cols) * x.es,
                  (double)x.g->n * x.b * (double)nd.cols * nd.np, x.s);
-    if (launch_ema_general(x.dt, a, R, stage, grid, lds, x.s)) {
-      set_error("sg2v_count: no eMA variant for R=%d", R);
-      return SG2V_EINVAL;
-    }
+    ST_TRY(launch_general(x, a));
   }
   if (x.dt == DT_U64) launch_zero_pad(x.dt, Ms.p, x.g->n, Ms.ld, Ms.cols * x.b, x.s);
   norm(x, Ms);
@@ -954,9 +1047,12 @@ sg2v_status copy_capture(Ctx &x, const Capture &cap) {
   return SG2V_OK;
 }
 
-sg2v_status run_pass(Ctx &x, void *result, int *Eout, const Capture *cap) {
+sg2v_status run_pass(Ctx &x, void *result, int *Eout, const Capture *cap, int stop_node = -1) {
   for (size_t q = 0; q < x.pp.steps.size(); ++q) {
     const Step &st = x.pp.steps[q];
+    if (st.node == stop_node && (st.kind == S_EMA_SINGLE || st.kind == S_EMA_GENERAL ||
+                                 st.kind == S_ROOT))
+      break;
     switch (st.kind) {
       case S_HIST: ST_TRY(step_hist(x, st.node)); break;
       case S_SPMM: ST_TRY(step_spmm(x, st.node)); break;
@@ -1015,7 +1111,7 @@ int choose_batch(const Plan &P, int ncol, int dt, int64_t n, int64_t n_slots) {
   int64_t budget = tu.budget_bytes > 0 ? tu.budget_bytes : (int64_t)(fr * 0.85);
   while (b > 1) {
     PassPlan pp;
-    build_pass(P, n, b, dt, pick_G(dt, widest_passive * b), n_slots, pp, -1, 0);
+    build_pass(P, n, b, dt, pick_G(dt, widest_passive * b), n_slots, pp, PassOpts());
     if (pp.arena <= budget) break;
     b = (b + 1) / 2;
   }
@@ -1023,7 +1119,7 @@ int choose_batch(const Plan &P, int ncol, int dt, int64_t n, int64_t n_slots) {
 }
 
 sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_colorings *c,
-                    sg2v_mode mode, int b, hipStream_t s, int debug_node, int debug_kind) {
+                    sg2v_mode mode, int b, hipStream_t s, const PassOpts &opt) {
   x.P = &plan->p;
   x.g = g;
   x.c = c;
@@ -1032,16 +1128,25 @@ sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_col
   x.b = b;
   x.s = s;
   x.ws = &workspace();
-  hipDeviceProp_t prop;
-  HIP_TRY(hipGetDeviceProperties(&prop, g->device));
-  x.cu_count = prop.multiProcessorCount;
-  x.lds_max = prop.sharedMemPerBlock;
+  {
+    static std::mutex mu;
+    static std::map<int, std::pair<int, size_t>> props;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = props.find(g->device);
+    if (it == props.end()) {
+      hipDeviceProp_t prop;
+      HIP_TRY(hipGetDeviceProperties(&prop, g->device));
+      it = props.emplace(g->device, std::make_pair(prop.multiProcessorCount,
+                                                   (size_t)prop.sharedMemPerBlock)).first;
+    }
+    x.cu_count = it->second.first;
+    x.lds_max = it->second.second;
+  }
   ST_TRY(plan_device(plan->p, g->device, s, &x.dp));
   int64_t widest = 1;
   for (auto &nd : plan->p.nodes)
     if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? plan->p.k : nd.cols);
-  build_pass(plan->p, g->n, b, x.dt, pick_G(x.dt, widest * b), g->n_slots, x.pp, debug_node,
-             debug_kind);
+  build_pass(plan->p, g->n, b, x.dt, pick_G(x.dt, widest * b), g->n_slots, x.pp, opt);
   sg2v_tuning_t tu = tuning();
   if (tu.budget_bytes > 0 && x.pp.arena > tu.budget_bytes) {
     set_error("sg2v_count: one colouring needs %lld bytes, budget is %lld",
@@ -1079,7 +1184,7 @@ extern "C" sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g,
     const int dt = dtype_of(mode);
     const int b = choose_batch(P, ncol, dt, g->n, g->n_slots);
     Ctx x;
-    ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, b, s, -1, 0));
+    ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, b, s, PassOpts()));
     ST_TRY(x.ws->result.ensure((size_t)ncol * 12 + 64));
     void *res = x.ws->result.p;
     int *Ed = (int *)((char *)res + (size_t)ncol * 8);
@@ -1089,7 +1194,7 @@ extern "C" sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g,
       if (bb != x.b) {
         // last, smaller pass: tables of the full batch still fit
         x.b = bb;
-        build_pass(P, g->n, bb, x.dt, x.pp.G, g->n_slots, x.pp, -1, 0);
+        build_pass(P, g->n, bb, x.dt, x.pp.G, g->n_slots, x.pp, PassOpts());
         ST_TRY(bind_tables(x));
       }
       x.j0 = j0;
@@ -1138,7 +1243,9 @@ extern "C" sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph 
   }
   hipStream_t s = (hipStream_t)stream;
   Ctx x;
-  ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, 1, s, node, kind));
+  PassOpts opt;
+  opt.keep.push_back({node, kind});
+  ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, 1, s, opt));
   ST_TRY(x.ws->result.ensure((size_t)c->count * 12 + 64));
   void *res = x.ws->result.p;
   int *Ed = (int *)((char *)res + (size_t)c->count * 8);
@@ -1172,11 +1279,222 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
   return SG2V_OK;
 }
 
-extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *, const sg2v_graph *,
-                                       const sg2v_colorings *, sg2v_mode, const double *, void *,
-                                       void *) {
-  set_error("sg2v_count_grad: not available in this build");
-  return SG2V_EINVAL;
+// Reverse-mode derivative of f = sum_j g_j * colourful_j with respect to the
+// CSR weights.  Splits are visited in reverse topological order with the
+// adjoint Mbar_s of each node complete (all its consumers come later in the
+// forward order).  For a split s = (a, p), B = A_G M_p, M_s = eMA(M_a, B):
+//   Mbar_a += sum over C containing I_a of Mbar_s(i, C) B(i, C \ I_a)
+//   Bbar    = sum over C containing I_p of Mbar_s(i, C) M_a(i, C \ I_p)
+//   grad[e = i->j] += sum_c Bbar(i, c) M_p(j, c)
+//   Mbar_p += A_G Bbar                       (A_G symmetric)
+// The forward tables M_a, M_p and B of each split are recomputed by a forward
+// pass that stops before the split, not stored.
+extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *g,
+                                       const sg2v_colorings *c, sg2v_mode mode,
+                                       const double *grad_colorful, void *grad_w,
+                                       void *stream) {
+  ST_TRY(check_inputs(plan, g, c, mode));
+  if (mode != SG2V_FP64) {
+    set_error("sg2v_count_grad: only SG2V_FP64 is supported");
+    return SG2V_EINVAL;
+  }
+  if (!grad_colorful || !grad_w) {
+    set_error("sg2v_count_grad: null gradient buffer");
+    return SG2V_EINVAL;
+  }
+  const Plan &P = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  sg2v_graph *gg = (sg2v_graph *)g;
+  launch_fill_value(DT_F64, grad_w, g->nnz, 0.0, s);
+  HIP_TRY(hipGetLastError());
+  if (P.root_kind == ROOT_VERTEX) {
+    HIP_TRY(hipStreamSynchronize(s));
+    return SG2V_OK;
+  }
+  const size_t nn = P.nodes.size();
+  int64_t widest = 1;
+  for (auto &nd : P.nodes)
+    if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? P.k : nd.cols);
+  const int G = pick_G(DT_F64, widest);
+  const int64_t align = std::max<int64_t>(16, (int64_t)G * 2);
+  // adjoint tables of every node with more than one vertex, plus Bbar
+  std::vector<int64_t> off(nn, -1), ld(nn, 0);
+  int64_t top = 0, bbar_ld = 0;
+  for (size_t q = 0; q < nn; ++q) {
+    const Node &nd = P.nodes[q];
+    if (nd.n_passive_uses > 0) bbar_ld = std::max(bbar_ld, round_up(nd.size == 1 ? P.k : nd.cols, align));
+    if (nd.size == 1) continue;
+    ld[q] = round_up(nd.cols, align);
+    off[q] = top;
+    top += round_up(g->n * ld[q] * 8, 256);
+  }
+  const int64_t bbar_off = top;
+  top += round_up(g->n * bbar_ld * 8, 256);
+  Workspace &ws = workspace();
+  ST_TRY(ws.grad.ensure(top));
+  char *gbase = (char *)ws.grad.p;
+  double *bbar = (double *)(gbase + bbar_off);
+  auto mbar = [&](int q) { return (double *)(gbase + off[q]); };
+
+  for (int j = 0; j < c->count; ++j) {
+    launch_fill_value(DT_F64, gbase, bbar_off / 8, 0.0, s);
+    launch_fill_value(DT_F64, mbar(P.root), g->n * ld[P.root], grad_colorful[j], s);
+    for (int q = (int)nn - 1; q >= 0; --q) {
+      const Node &nd = P.nodes[q];
+      if (nd.size == 1) continue;
+      const Node &A = P.nodes[nd.active];
+      const Node &Pn = P.nodes[nd.passive];
+      PassOpts opt;
+      opt.no_fuse = true;
+      if (A.size > 1) opt.keep.push_back({nd.active, 0});
+      if (Pn.size > 1) opt.keep.push_back({nd.passive, 0});
+      opt.keep.push_back({nd.passive, 1});
+      Ctx x;
+      ST_TRY(prepare(x, plan, gg, c, mode, 1, s, opt));
+      ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
+      x.j0 = j;
+      ST_TRY(run_pass(x, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr,
+                      q));
+      Tab &Bp = x.pp.B[nd.passive];
+      const int64_t cs = nd.cols, ca = A.size == 1 ? P.k : A.cols, cp = Bp.cols;
+      // Mbar_a += eMA^T over the active index
+      if (A.size > 1) {
+        EmaArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.Ma = mbar(q);
+        a.lda = ld[q];
+        a.Ca = (int32_t)cs;
+        a.B = Bp.p;
+        a.ldb = Bp.ld;
+        a.Cb = (int32_t)cp;
+        a.Ms = mbar(nd.active);
+        a.lds = ld[nd.active];
+        a.Cs = (int32_t)ca;
+        a.pairs = x.dp.tr_a[q];
+        a.np = nd.np_ta;
+        a.n = g->n;
+        a.ovf = x.ovf;
+        a.accumulate = 1;
+        ProfScope ps(SG2V_K_EMA_GENERAL, (double)g->n * (cs + cp + 2 * ca) * 8,
+                     (double)g->n * ca * nd.np_ta, s);
+        ST_TRY(launch_general(x, a));
+      }
+      // Bbar over the passive index
+      {
+        EmaArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.Ms = bbar;
+        a.lds = bbar_ld;
+        a.Cs = (int32_t)cp;
+        a.n = g->n;
+        a.colors = c->d;
+        a.j0 = j;
+        a.ovf = x.ovf;
+        if (A.size > 1) {
+          Tab &Ma = x.pp.M[nd.active];
+          a.Ma = mbar(q);
+          a.lda = ld[q];
+          a.Ca = (int32_t)cs;
+          a.B = Ma.p;
+          a.ldb = Ma.ld;
+          a.Cb = (int32_t)ca;
+          a.pairs = x.dp.tr_p[q];
+          a.np = nd.np_tp;
+          ProfScope ps(SG2V_K_EMA_GENERAL, (double)g->n * (cs + ca + cp) * 8,
+                       (double)g->n * cp * nd.np_tp, s);
+          ST_TRY(launch_general(x, a));
+        } else {
+          a.B = mbar(q);
+          a.ldb = ld[q];
+          a.Cb = (int32_t)cs;
+          a.drop = x.dp.add[q];
+          const int64_t cpad = round_up(cp, 64);
+          const int64_t rpi = cpad >= 256 ? 1 : 256 / cpad;
+          dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((g->n + rpi - 1) / rpi, 4096)), 1);
+          ProfScope ps(SG2V_K_EMA_SINGLE, (double)g->n * (cs + cp) * 8, (double)g->n * cp, s);
+          launch_ema_single(DT_F64, a, grid, 0, s);
+        }
+      }
+      // edge gradient
+      {
+        SddmmArgs d;
+        d.row_ptr = g->row_ptr;
+        d.col_idx = g->col_idx;
+        d.Bbar = bbar;
+        d.ldb = bbar_ld;
+        d.Mp = Pn.size > 1 ? x.pp.M[nd.passive].p : nullptr;
+        d.ldm = Pn.size > 1 ? x.pp.M[nd.passive].ld : 0;
+        d.ncols = cp;
+        d.n = g->n;
+        d.colors = c->d;
+        d.j0 = j;
+        d.b = 1;
+        d.k = P.k;
+        d.grad = (double *)grad_w;
+        ProfScope ps(SG2V_K_SPMM, (double)g->nnz * 12 + (double)g->n * cp * 16,
+                     (double)g->nnz * cp, s);
+        launch_sddmm(DT_F64, d, s);
+      }
+      // Mbar_p += A_G Bbar
+      if (Pn.size > 1) {
+        UnitTable *U = nullptr;
+        ST_TRY(build_units(gg, x.pp.G, s, &U));
+        const int W = x.pp.G * 2;
+        SpmmArgs a;
+        a.col_idx = g->col_idx;
+        a.w = g->w;
+        a.task_row = g->task_row;
+        a.task_beg = g->task_beg;
+        a.task_len = g->task_len;
+        a.task_slot = g->task_slot;
+        a.unit_task = U->unit_task;
+        a.unit_rpw = U->unit_rpw;
+        a.unit_ntask = U->unit_ntask;
+        a.n_units = U->n_units;
+        a.M = bbar;
+        a.ldm = bbar_ld;
+        a.B = mbar(nd.passive);
+        a.ldb = ld[nd.passive];
+        a.partial = (char *)x.ws->arena.p + x.pp.partial_off;
+        a.ncols_valid = cp;
+        a.mx = nullptr;
+        a.ovf = x.ovf;
+        a.accumulate = 1;
+        a.chunk_jb = nullptr;
+        a.chunk_union = a.chunk_inter = nullptr;
+        a.colors = c->d;
+        a.j0 = j;
+        a.n = g->n;
+        const int64_t chunks = (cp + W - 1) / W;
+        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
+                  (unsigned)chunks);
+        {
+          ProfScope ps(SG2V_K_SPMM, 2.0 * g->n * cp * 8 + (double)chunks * g->nnz * 8,
+                       (double)g->nnz * cp, s);
+          if (launch_spmm(DT_F64, a, x.pp.G, grid, s)) {
+            set_error("sg2v_count_grad: no SpMM variant for G=%d", x.pp.G);
+            return SG2V_EINVAL;
+          }
+        }
+        CombineArgs cb;
+        cb.partial = a.partial;
+        cb.B = a.B;
+        cb.ld = a.ldb;
+        cb.ncols_valid = cp;
+        cb.long_row = g->long_row;
+        cb.long_slot0 = g->long_slot0;
+        cb.long_nslot = g->long_nslot;
+        cb.n_long = g->n_long;
+        cb.mx = nullptr;
+        cb.ovf = x.ovf;
+        cb.accumulate = 1;
+        launch_spmm_combine(DT_F64, cb, s);
+      }
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return SG2V_OK;
 }
 
 extern "C" sg2v_status sg2v_set_tuning(const sg2v_tuning_t *t) {
@@ -1208,6 +1526,10 @@ extern "C" void sg2v_plan_destroy(sg2v_plan *plan) {
     for (void *q : d.pairs) (void)hipFree(q);
     for (void *q : d.drop) (void)hipFree(q);
     (void)hipFree(d.root_list);
+    for (void *q : d.tr_a) (void)hipFree(q);
+    for (void *q : d.tr_p) (void)hipFree(q);
+    for (void *q : d.add) (void)hipFree(q);
+    for (auto &kv : d.chunks) (void)hipFree(kv.second);
     (void)hipSetDevice(cur);
   }
   delete plan;

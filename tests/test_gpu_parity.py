@@ -113,27 +113,46 @@ def test_random_trees_all_modes(small_rmat):
             assert r32["colorful"][j] == pytest.approx(ref64[j][0], rel=FP32_TOL)
 
 
+def _colex_sets(k, m):
+    from itertools import combinations
+    return sorted(combinations(range(k), m), key=lambda s: sum(math.comb(c, i + 1) for i, c in enumerate(s)))
+
+
 @pytest.mark.parametrize("mode", ["u64", "fp64", "fp32s"])
-def test_intermediate_tables(small_rmat, mode):
-    """Every materialised table M_s and B = A M_p against the oracle's."""
+@pytest.mark.parametrize("skip", [False, True])
+def test_intermediate_tables(small_rmat, mode, skip):
+    """Every materialised table M_s and B = A M_p against the oracle's.  With
+    colour skipping, B(i, C) is only defined for sets C not holding i's colour
+    (the only entries any multiply-add reads) and is zero elsewhere."""
     G = small_rmat
-    for par, k in ((gg.BINTREE7, 7), (gg.CATERPILLAR10, 10)):
-        p = sg.Plan(par, k)
-        g = sg.Graph.from_csr(G)
-        c = sg.Colorings(g, k, 3, 2)
-        col1 = O.colors(G.n, k, 3, 1)
-        om = O.U64 if mode == "u64" else O.FP64
-        info = p.info()
-        for idx, nd in enumerate(p.nodes()):
-            ref_M = O.node_table(G, par, k, col1, nd.vertex, nd.n_kept, mode=om)
-            if nd.size > 1 and idx != info.root_node:
-                say("table M", par, idx, mode)
-                got = sg.debug_table(p, g, c, idx, 0, which=1, mode=mode)
-                _cmp(got, ref_M, mode)
-            if nd.is_passive:
-                say("table B", par, idx, mode)
-                got = sg.debug_table(p, g, c, idx, 1, which=1, mode=mode)
-                _cmp(got, O.neighbour_sum(G, ref_M, mode=om), mode)
+    old = sg.get_tuning()
+    sg.set_tuning(flags=0 if skip else sg.TUNE_NO_COLOR_SKIP)
+    try:
+        for par, k in ((gg.BINTREE7, 7), (gg.CATERPILLAR10, 10)):
+            p = sg.Plan(par, k)
+            g = sg.Graph.from_csr(G)
+            c = sg.Colorings(g, k, 3, 2)
+            col1 = O.colors(G.n, k, 3, 1)
+            om = O.U64 if mode == "u64" else O.FP64
+            info = p.info()
+            for idx, nd in enumerate(p.nodes()):
+                ref_M = O.node_table(G, par, k, col1, nd.vertex, nd.n_kept, mode=om)
+                if nd.size > 1 and idx != info.root_node:
+                    say("table M", par, idx, mode, skip)
+                    got = sg.debug_table(p, g, c, idx, 0, which=1, mode=mode)
+                    _cmp(got, ref_M, mode)
+                if nd.is_passive:
+                    say("table B", par, idx, mode, skip)
+                    got = sg.debug_table(p, g, c, idx, 1, which=1, mode=mode)
+                    ref_B = O.neighbour_sum(G, ref_M, mode=om)
+                    if skip and nd.size > 1:
+                        sets = _colex_sets(k, nd.size)
+                        holds = np.array([[c in s for s in sets] for c in range(k)])[col1]
+                        ref_B = np.where(holds, ref_B.dtype.type(0), ref_B)
+                        got = np.where(holds, got.dtype.type(0), got)
+                    _cmp(got, ref_B, mode)
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
 
 
 def _cmp(got, ref, mode):
@@ -176,7 +195,7 @@ def test_batching_invariance(small_rmat):
         np.testing.assert_array_equal(res[1], res[5])
         np.testing.assert_allclose(res[("f", 1)], res[("f", 5)], rtol=1e-6)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes)
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
 
 
 def test_spmm_widths_agree(small_rmat):
@@ -188,12 +207,13 @@ def test_spmm_widths_agree(small_rmat):
     old = sg.get_tuning()
     try:
         for w in (8, 16, 32, 64):
-            sg.set_tuning(spmm_width=w)
-            say("spmm width", w)
-            got = sg.count(p, g, c, "u64")["colorful_u64"]
-            assert [int(x) for x in got] == ref
+            for fl in (0, sg.TUNE_NO_COLOR_SKIP):
+                sg.set_tuning(spmm_width=w, flags=fl)
+                say("spmm width", w, "flags", fl)
+                got = sg.count(p, g, c, "u64")["colorful_u64"]
+                assert [int(x) for x in got] == ref
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes)
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
 
 
 def test_edge_cases():
