@@ -61,6 +61,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  uint64_t gen = 0;  // bumped on every reallocation (captured graphs hold raw pointers)
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
@@ -79,6 +80,7 @@ struct DevBuf {
       return SG2V_ENOMEM;
     }
     bytes = want;
+    ++gen;
     return SG2V_OK;
   }
 };
@@ -123,12 +125,15 @@ Profiler &profiler() {
   return p;
 }
 
+thread_local bool t_capturing = false;  // inside hipStreamBeginCapture ... EndCapture
+
 // brackets the kernel launches of its lifetime with events when profiling
 struct ProfScope {
   bool on;
   ProfRec r;
   hipStream_t s;
-  ProfScope(int kind, double bytes, double work, hipStream_t st) : on(profiler().on), s(st) {
+  ProfScope(int kind, double bytes, double work, hipStream_t st)
+      : on(profiler().on && !t_capturing), s(st) {
     if (!on) return;
     r.kind = kind;
     r.bytes = bytes;
@@ -401,7 +406,12 @@ extern "C" sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *
   return SG2V_OK;
 }
 
-extern "C" void sg2v_graph_destroy(sg2v_graph *g) { delete g; }
+void drop_batch_graphs(const sg2v_graph *g);
+
+extern "C" void sg2v_graph_destroy(sg2v_graph *g) {
+  drop_batch_graphs(g);
+  delete g;
+}
 
 extern "C" sg2v_status sg2v_color(const sg2v_graph *g, int32_t k, uint64_t seed, int32_t first,
                                   int32_t n_colorings, void *stream, sg2v_colorings **out) {
@@ -1161,6 +1171,67 @@ sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_col
   return bind_tables(x);
 }
 
+// Upload everything a pass over b colourings needs (SpMM units, colour-skip
+// masks) so that the pass itself only enqueues kernels.
+sg2v_status prewarm(Ctx &x, int b) {
+  if (b < 1) return SG2V_OK;
+  PassPlan pp;
+  build_pass(*x.P, x.g->n, b, x.dt, x.pp.G, x.g->n_slots, pp, PassOpts());
+  UnitTable *U = nullptr;
+  ST_TRY(build_units(x.g, x.pp.G, x.s, &U));
+  if (tuning().flags & SG2V_TUNE_NO_COLOR_SKIP) return SG2V_OK;
+  const int W = x.pp.G * (x.dt == DT_F32 ? 4 : 2);
+  const int keep_b = x.b;
+  x.b = b;
+  for (auto &st : pp.steps)
+    if (st.kind == S_SPMM) {
+      const int32_t *a;
+      const uint32_t *u, *i;
+      sg2v_status r = chunk_masks(x, st.node, W, &a, &u, &i);
+      if (r != SG2V_OK) {
+        x.b = keep_b;
+        return r;
+      }
+    }
+  x.b = keep_b;
+  return SG2V_OK;
+}
+
+// Enqueue every pass for the ncol colourings of x.c (no host synchronisation):
+// raw colourful sums to res[j] (double or uint64), FP32S frame exponents to
+// Ed[j].  x must come from prepare() with batch b, prewarmed for b and for the
+// last, smaller pass.
+sg2v_status enqueue_count(Ctx &x, int ncol, int b, void *res, int *Ed) {
+  for (int j0 = 0; j0 < ncol; j0 += b) {
+    const int bb = std::min(b, ncol - j0);
+    if (bb != x.b) {
+      // last, smaller pass: tables of the full batch still fit
+      x.b = bb;
+      build_pass(*x.P, x.g->n, bb, x.dt, x.pp.G, x.g->n_slots, x.pp, PassOpts());
+      ST_TRY(bind_tables(x));
+    }
+    x.j0 = j0;
+    ST_TRY(run_pass(x, res, Ed, nullptr));
+  }
+  return SG2V_OK;
+}
+
+void finish_counts(const Plan &P, int ncol, int dt, const double *rf, const uint64_t *ru,
+                   const int *E, double *colorful, uint64_t *colorful_u64, double *estimate,
+                   double *mean_estimate) {
+  double mean = 0.0;
+  for (int j = 0; j < ncol; ++j) {
+    double v = dt == DT_U64 ? (double)ru[j] : rf[j];
+    if (dt == DT_F32) v = std::ldexp(v, E[j]);
+    if (colorful) colorful[j] = v;
+    if (colorful_u64) colorful_u64[j] = dt == DT_U64 ? ru[j] : 0;
+    const double est = v / (P.P * (double)P.alpha);
+    if (estimate) estimate[j] = est;
+    mean += est;
+  }
+  if (mean_estimate) *mean_estimate = mean / ncol;
+}
+
 }  // namespace
 
 extern "C" sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g,
@@ -1171,57 +1242,39 @@ extern "C" sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g,
   const Plan &P = plan->p;
   hipStream_t s = (hipStream_t)stream;
   const int ncol = c->count;
+  const int dt = dtype_of(mode);
   std::vector<double> raw_f(ncol, 0.0);
   std::vector<uint64_t> raw_u(ncol, 0);
   std::vector<int> Eh(ncol, 0);
   int ovf_h = 0;
   if (P.root_kind == ROOT_VERTEX) {
+    // every vertex is one colourful map of a one-vertex template
     for (int j = 0; j < ncol; ++j) {
-      raw_f[j] = (double)g->n;  // every vertex is one colourful map of a one-vertex template
+      raw_f[j] = (double)g->n;
       raw_u[j] = (uint64_t)g->n;
     }
+    Eh.assign(ncol, 0);
   } else {
-    const int dt = dtype_of(mode);
     const int b = choose_batch(P, ncol, dt, g->n, g->n_slots);
     Ctx x;
     ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, b, s, PassOpts()));
+    ST_TRY(prewarm(x, b));
+    ST_TRY(prewarm(x, ncol % b));
     ST_TRY(x.ws->result.ensure((size_t)ncol * 12 + 64));
     void *res = x.ws->result.p;
     int *Ed = (int *)((char *)res + (size_t)ncol * 8);
     launch_fill_u32((unsigned *)x.ovf, 1, 0u, s);
-    for (int j0 = 0; j0 < ncol; j0 += b) {
-      const int bb = std::min(b, ncol - j0);
-      if (bb != x.b) {
-        // last, smaller pass: tables of the full batch still fit
-        x.b = bb;
-        build_pass(P, g->n, bb, x.dt, x.pp.G, g->n_slots, x.pp, PassOpts());
-        ST_TRY(bind_tables(x));
-      }
-      x.j0 = j0;
-      ST_TRY(run_pass(x, res, Ed, nullptr));
-    }
-    if (dt == DT_U64) {
-      HIP_TRY(hipMemcpyAsync(raw_u.data(), res, ncol * 8, hipMemcpyDeviceToHost, s));
-    } else {
-      HIP_TRY(hipMemcpyAsync(raw_f.data(), res, ncol * 8, hipMemcpyDeviceToHost, s));
-    }
+    ST_TRY(enqueue_count(x, ncol, b, res, Ed));
+    HIP_TRY(hipMemcpyAsync(dt == DT_U64 ? (void *)raw_u.data() : (void *)raw_f.data(), res,
+                           ncol * 8, hipMemcpyDeviceToHost, s));
     if (dt == DT_F32) HIP_TRY(hipMemcpyAsync(Eh.data(), Ed, ncol * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&ovf_h, x.ovf, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (dt == DT_U64)
-      for (int j = 0; j < ncol; ++j) raw_f[j] = (double)raw_u[j];
-    if (dt == DT_F32)
-      for (int j = 0; j < ncol; ++j) raw_f[j] = std::ldexp(raw_f[j], Eh[j]);
   }
-  double mean = 0.0;
-  for (int j = 0; j < ncol; ++j) {
-    if (colorful) colorful[j] = raw_f[j];
-    if (colorful_u64) colorful_u64[j] = raw_u[j];
-    const double est = raw_f[j] / (P.P * (double)P.alpha);
-    if (estimate) estimate[j] = est;
-    mean += est;
-  }
-  if (mean_estimate) *mean_estimate = mean / ncol;
+  finish_counts(P, ncol, P.root_kind == ROOT_VERTEX ? DT_F64 : dt, raw_f.data(), raw_u.data(),
+                Eh.data(), colorful, colorful_u64, estimate, mean_estimate);
+  if (colorful_u64 && P.root_kind == ROOT_VERTEX)
+    for (int j = 0; j < ncol; ++j) colorful_u64[j] = raw_u[j];
   if (overflow) *overflow = ovf_h;
   return SG2V_OK;
 }
@@ -1260,6 +1313,49 @@ extern "C" sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph 
   return SG2V_OK;
 }
 
+namespace {
+
+// One captured multi-template count: colourings of every plan plus all of
+// their passes, instantiated once and replayed while the workspace buffers
+// it captured are unchanged.
+struct BatchGraph {
+  std::vector<const sg2v_plan *> plans;
+  const sg2v_graph *g = nullptr;
+  uint64_t seed = 0;
+  int ncol = 0, mode = 0;
+  sg2v_tuning_t tune{};
+  uint64_t gens[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<std::unique_ptr<sg2v_colorings>> cols;
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
+  ~BatchGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchGraph>> g_batch_cache;
+
+bool same_tuning(const sg2v_tuning_t &a, const sg2v_tuning_t &b) {
+  return a.spmm_width == b.spmm_width && a.ema_rows == b.ema_rows && a.batch == b.batch &&
+         a.flags == b.flags && a.budget_bytes == b.budget_bytes;
+}
+
+void ws_gens(Workspace &ws, uint64_t *out) {
+  out[0] = ws.arena.gen;
+  out[1] = ws.small.gen;
+  out[2] = ws.partial.gen;
+  out[3] = ws.result.gen;
+  out[4] = ws.ovf.gen;
+  out[5] = ws.grad.gen;
+}
+
+}  // namespace
+
+// Several templates, n_colorings colourings each, recorded as one HIP graph
+// (colouring kernels and every pass of every template) and launched with a
+// single hipGraphLaunch.  The executable graph is cached and replayed by later
+// calls with the same arguments while the workspace is unchanged.
 extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n_plans,
                                         const sg2v_graph *g, uint64_t seed, int32_t n_colorings,
                                         sg2v_mode mode, void *stream, double *colorful,
@@ -1268,14 +1364,117 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
     set_error("sg2v_count_batch: bad argument");
     return SG2V_EINVAL;
   }
-  for (int p = 0; p < n_plans; ++p) {
-    sg2v_colorings *c = nullptr;
-    ST_TRY(sg2v_color(g, plans[p]->p.k, seed, 0, n_colorings, stream, &c));
-    std::unique_ptr<sg2v_colorings> hold(c);
-    ST_TRY(sg2v_count(plans[p], g, c, mode, stream, colorful ? colorful + (size_t)p * n_colorings : nullptr,
-                      nullptr, estimate ? estimate + (size_t)p * n_colorings : nullptr, nullptr,
-                      nullptr));
+  for (int p = 0; p < n_plans; ++p)
+    if (!plans[p] || plans[p]->p.root_kind == ROOT_VERTEX) {
+      set_error("sg2v_count_batch: plan %d is null or a one-vertex template", p);
+      return SG2V_EINVAL;
+    }
+  if (mode != SG2V_FP64 && mode != SG2V_FP32S && mode != SG2V_U64) {
+    set_error("sg2v_count_batch: unknown mode %d", mode);
+    return SG2V_EINVAL;
   }
+  if (mode == SG2V_U64 && g->w) {
+    set_error("sg2v_count_batch: U64 mode counts the 0/1 adjacency; the graph has weights");
+    return SG2V_EINVAL;
+  }
+  hipStream_t us = (hipStream_t)stream;
+  const int dt = dtype_of(mode);
+  const int ncol = n_colorings;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  Workspace &ws = workspace();
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+
+  // colourings and contexts (all uploads and allocations happen here)
+  std::unique_ptr<BatchGraph> bg(new BatchGraph());
+  bg->plans.assign(plans, plans + n_plans);
+  bg->g = g;
+  bg->seed = seed;
+  bg->ncol = ncol;
+  bg->mode = mode;
+  bg->tune = tuning();
+  bg->device = dev;
+  std::vector<Ctx> xs(n_plans);
+  std::vector<int> bs(n_plans);
+  for (int p = 0; p < n_plans; ++p) {
+    std::unique_ptr<sg2v_colorings> c(new sg2v_colorings());
+    c->device = dev;
+    c->n = g->n;
+    c->k = plans[p]->p.k;
+    c->count = ncol;
+    c->seed = seed;
+    HIP_TRY(hipMalloc((void **)&c->d, g->n * ncol));
+    bs[p] = choose_batch(plans[p]->p, ncol, dt, g->n, g->n_slots);
+    ST_TRY(prepare(xs[p], plans[p], (sg2v_graph *)g, c.get(), mode, bs[p], us, PassOpts()));
+    ST_TRY(prewarm(xs[p], bs[p]));
+    ST_TRY(prewarm(xs[p], ncol % bs[p]));
+    bg->cols.push_back(std::move(c));
+  }
+  ST_TRY(ws.result.ensure((size_t)n_plans * ncol * 12 + 64));
+  HIP_TRY(hipStreamSynchronize(us));
+
+  // reuse a cached executable graph if every input and buffer is unchanged
+  uint64_t gens[6];
+  ws_gens(ws, gens);
+  BatchGraph *hit = nullptr;
+  for (auto &e : g_batch_cache) {
+    if (e->g == g && e->seed == seed && e->ncol == ncol && e->mode == mode && e->device == dev &&
+        e->plans == bg->plans && same_tuning(e->tune, bg->tune) &&
+        std::equal(gens, gens + 6, e->gens))
+      hit = e.get();
+  }
+  char *res = (char *)ws.result.p;
+  int *Ed = (int *)(res + (size_t)n_plans * ncol * 8);
+  if (!hit) {
+    // the prepares above may have grown the workspace: rebind every context
+    for (int p = 0; p < n_plans; ++p) {
+      xs[p].ovf = (int *)ws.ovf.p;
+      ST_TRY(bind_tables(xs[p]));
+    }
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    sg2v_status st = SG2V_OK;
+    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      t_capturing = true;
+      launch_fill_u32((unsigned *)ws.ovf.p, 1, 0u, cs);
+      for (int p = 0; p < n_plans && st == SG2V_OK; ++p) {
+        launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, cs);
+        xs[p].s = cs;
+        xs[p].c = bg->cols[p].get();
+        st = enqueue_count(xs[p], ncol, bs[p], res + (size_t)p * ncol * 8, Ed + (size_t)p * ncol);
+      }
+      t_capturing = false;
+      hipError_t he2 = hipStreamEndCapture(cs, &graph);
+      if (he == hipSuccess) he = he2;
+    }
+    if (he == hipSuccess && st == SG2V_OK) he = hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (st != SG2V_OK) return st;
+    if (he != hipSuccess) {
+      set_error("sg2v_count_batch: graph capture failed: %s", hipGetErrorString(he));
+      return SG2V_EDEVICE;
+    }
+    ws_gens(ws, bg->gens);
+    g_batch_cache.push_back(std::move(bg));
+    if (g_batch_cache.size() > 8) g_batch_cache.erase(g_batch_cache.begin());
+    hit = g_batch_cache.back().get();
+  }
+  HIP_TRY(hipGraphLaunch(hit->exec, us));
+  std::vector<double> rf((size_t)n_plans * ncol);
+  std::vector<uint64_t> ru((size_t)n_plans * ncol);
+  std::vector<int> E((size_t)n_plans * ncol, 0);
+  HIP_TRY(hipMemcpyAsync(dt == DT_U64 ? (void *)ru.data() : (void *)rf.data(), res,
+                         (size_t)n_plans * ncol * 8, hipMemcpyDeviceToHost, us));
+  if (dt == DT_F32)
+    HIP_TRY(hipMemcpyAsync(E.data(), Ed, (size_t)n_plans * ncol * 4, hipMemcpyDeviceToHost, us));
+  HIP_TRY(hipStreamSynchronize(us));
+  for (int p = 0; p < n_plans; ++p)
+    finish_counts(plans[p]->p, ncol, dt, rf.data() + (size_t)p * ncol, ru.data() + (size_t)p * ncol,
+                  E.data() + (size_t)p * ncol, colorful ? colorful + (size_t)p * ncol : nullptr,
+                  nullptr, estimate ? estimate + (size_t)p * ncol : nullptr, nullptr);
   return SG2V_OK;
 }
 
@@ -1517,8 +1716,28 @@ extern "C" sg2v_status sg2v_get_tuning(sg2v_tuning_t *t) {
   return SG2V_OK;
 }
 
+void drop_batch_graphs(const sg2v_graph *g) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (size_t i = 0; i < g_batch_cache.size();) {
+    if (g_batch_cache[i]->g == g)
+      g_batch_cache.erase(g_batch_cache.begin() + i);
+    else
+      ++i;
+  }
+}
+
 extern "C" void sg2v_plan_destroy(sg2v_plan *plan) {
   if (!plan) return;
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (size_t i = 0; i < g_batch_cache.size();) {
+      auto &e = g_batch_cache[i];
+      if (std::find(e->plans.begin(), e->plans.end(), plan) != e->plans.end())
+        g_batch_cache.erase(g_batch_cache.begin() + i);
+      else
+        ++i;
+    }
+  }
   for (auto &d : plan->p.dev) {
     int cur = 0;
     (void)hipGetDevice(&cur);
