@@ -248,6 +248,17 @@ typedef struct {
 sg2v_status sg2v_set_tuning(const sg2v_tuning_t *t);
 sg2v_status sg2v_get_tuning(sg2v_tuning_t *t);
 
+/* Autotuner: time sg2v_count of `plan` on `g` (n_colorings probe colourings,
+ * `mode`) over a small set of candidate settings -- SpMM chunk width, colour
+ * skipping, eMA rows per tile, colourings per pass -- and install the fastest
+ * with sg2v_set_tuning.  Results are cached per (template, n, nnz, mode,
+ * n_colorings) in the process and, if the environment variable
+ * SG2V_TUNE_CACHE names a file, in that file (one line per key).
+ *   out : nullable; receives the chosen settings.
+ * Errors: as sg2v_count. */
+sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g, sg2v_mode mode,
+                          int32_t n_colorings, void *stream, sg2v_tuning_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,7 +65,7 @@ EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_des
            "sg2v_plan_info", "sg2v_plan_node", "sg2v_plan_pairs", "sg2v_graph_create", "sg2v_graph_destroy",
            "sg2v_color", "sg2v_colorings_destroy", "sg2v_colorings_download", "sg2v_count",
            "sg2v_count_batch", "sg2v_count_grad", "sg2v_debug_table", "sg2v_set_tuning",
-           "sg2v_get_tuning", "sg2v_profile_start", "sg2v_profile_stop"]
+           "sg2v_get_tuning", "sg2v_profile_start", "sg2v_profile_stop", "sg2v_autotune"]
 
 KERNEL_KINDS = ["color", "hist", "spmm", "spmm_combine", "ema_general", "ema_single", "root"]
 
@@ -106,6 +106,7 @@ def lib():
         L.sg2v_debug_table.argtypes = [P, P, P, i32, i32, i32, i32, P, P]
         L.sg2v_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.sg2v_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.sg2v_autotune.argtypes = [P, P, i32, i32, P, ctypes.POINTER(Tuning)]
         L.sg2v_profile_start.argtypes = []
         L.sg2v_profile_stop.argtypes = [ctypes.POINTER(ProfEntry)]
         for name in EXPORTS:
@@ -371,3 +372,13 @@ class SubgraphCount:
 
             cls._fn = _F
         return cls._fn.apply(w, plan, row_ptr, col_idx, seed, n_colorings)
+
+
+def autotune(plan: Plan, graph: Graph, mode="fp32s", n_colorings: int = 1, stream=None) -> Tuning:
+    """Time candidate settings for this template and graph and install the
+    fastest (sg2v_autotune)."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    t = Tuning()
+    _check(lib().sg2v_autotune(plan.h, graph.h, m, n_colorings, _stream(stream), ctypes.byref(t)),
+           "sg2v_autotune")
+    return t

@@ -6,7 +6,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1792,5 +1795,129 @@ extern "C" sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out) {
     p.pool.push_back(r.b);
   }
   p.recs.clear();
+  return SG2V_OK;
+}
+
+namespace {
+
+std::mutex g_autotune_mu;
+std::map<std::string, sg2v_tuning_t> g_autotune;
+
+std::string tune_key(const Plan &P, const sg2v_graph *g, sg2v_mode mode, int ncol) {
+  std::ostringstream k;
+  k << P.nodes[P.root].canon << "/k" << P.k << "/n" << g->n << "/nnz" << g->nnz << "/m" << mode
+    << "/c" << ncol;
+  return k.str();
+}
+
+void tune_file_load() {
+  const char *f = std::getenv("SG2V_TUNE_CACHE");
+  if (!f) return;
+  std::ifstream in(f);
+  std::string key;
+  sg2v_tuning_t t{};
+  while (in >> key >> t.spmm_width >> t.ema_rows >> t.batch >> t.flags >> t.budget_bytes)
+    g_autotune[key] = t;
+}
+
+void tune_file_store(const std::string &key, const sg2v_tuning_t &t) {
+  const char *f = std::getenv("SG2V_TUNE_CACHE");
+  if (!f) return;
+  std::ofstream out(f, std::ios::app);
+  out << key << " " << t.spmm_width << " " << t.ema_rows << " " << t.batch << " " << t.flags
+      << " " << t.budget_bytes << "\n";
+}
+
+}  // namespace
+
+extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g, sg2v_mode mode,
+                                     int32_t n_colorings, void *stream, sg2v_tuning_t *out) {
+  if (!plan || !g || n_colorings < 1) {
+    set_error("sg2v_autotune: bad argument");
+    return SG2V_EINVAL;
+  }
+  const std::string key = tune_key(plan->p, g, mode, n_colorings);
+  {
+    std::lock_guard<std::mutex> lk(g_autotune_mu);
+    static bool loaded = false;
+    if (!loaded) {
+      tune_file_load();
+      loaded = true;
+    }
+    auto it = g_autotune.find(key);
+    if (it != g_autotune.end()) {
+      ST_TRY(sg2v_set_tuning(&it->second));
+      if (out) *out = it->second;
+      return SG2V_OK;
+    }
+  }
+  const sg2v_tuning_t base = tuning();
+  sg2v_colorings *c = nullptr;
+  ST_TRY(sg2v_color(g, plan->p.k, 0x5EEDULL, 0, n_colorings, stream, &c));
+  std::unique_ptr<sg2v_colorings> hold(c);
+  std::vector<sg2v_tuning_t> cand;
+  const int widths[] = {16, 32, 64};
+  const int rows[] = {4, 8, 16};
+  for (int w : widths)
+    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP}) {
+      sg2v_tuning_t t = base;
+      t.spmm_width = w;
+      t.flags = (base.flags & ~SG2V_TUNE_NO_COLOR_SKIP) | fl;
+      cand.push_back(t);
+    }
+  sg2v_tuning_t best = base;
+  double best_ms = 1e300;
+  auto time_one = [&](const sg2v_tuning_t &t, double *ms) -> sg2v_status {
+    ST_TRY(sg2v_set_tuning(&t));
+    double cf;
+    ST_TRY(sg2v_count(plan, g, c, mode, stream, nullptr, nullptr, nullptr, &cf, nullptr));
+    auto t0 = std::chrono::steady_clock::now();
+    ST_TRY(sg2v_count(plan, g, c, mode, stream, nullptr, nullptr, nullptr, &cf, nullptr));
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return SG2V_OK;
+  };
+  sg2v_status st = SG2V_OK;
+  for (auto &t : cand) {
+    double ms;
+    if ((st = time_one(t, &ms)) != SG2V_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  if (st == SG2V_OK) {
+    // then rows per eMA tile and colourings per pass around the best width
+    std::vector<sg2v_tuning_t> more;
+    for (int r : rows) {
+      sg2v_tuning_t t = best;
+      t.ema_rows = r;
+      more.push_back(t);
+    }
+    for (int b : {1, 2, 4}) {
+      if (b > n_colorings) break;
+      sg2v_tuning_t t = best;
+      t.batch = b;
+      more.push_back(t);
+    }
+    for (auto &t : more) {
+      double ms;
+      if ((st = time_one(t, &ms)) != SG2V_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  }
+  if (st != SG2V_OK) {
+    (void)sg2v_set_tuning(&base);
+    return st;
+  }
+  ST_TRY(sg2v_set_tuning(&best));
+  {
+    std::lock_guard<std::mutex> lk(g_autotune_mu);
+    g_autotune[key] = best;
+    tune_file_store(key, best);
+  }
+  if (out) *out = best;
   return SG2V_OK;
 }

@@ -73,3 +73,21 @@ def test_batch_config_chung_lu_500k():
         say("oracle", par, f, cf64[p][0])
         assert cf64[p][0] == pytest.approx(f, rel=1e-12)
         assert cf32[p][0] == pytest.approx(f, rel=1e-5)
+
+
+def test_autotune_installs_a_candidate_and_keeps_results():
+    G = gg.rmat(12, 40_000, seed=9)
+    g = sg.Graph.from_csr(G)
+    p = sg.Plan(gg.CATERPILLAR10)
+    old = sg.get_tuning()
+    try:
+        c = sg.Colorings(g, 10, 5, 2)
+        ref = sg.count(p, g, c, "u64")["colorful_u64"].copy()
+        t = sg.autotune(p, g, "u64", 2)
+        cur = sg.get_tuning()
+        assert (cur.spmm_width, cur.ema_rows, cur.batch, cur.flags) == (
+            t.spmm_width, t.ema_rows, t.batch, t.flags)
+        assert t.spmm_width in (16, 32, 64)
+        np.testing.assert_array_equal(sg.count(p, g, c, "u64")["colorful_u64"], ref)
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
