@@ -76,12 +76,19 @@ class ProfEntry(ctypes.Structure):
 
 
 def lib():
-    """Load libsg2v.so (raises if it has not been built)."""
+    """Load libsg2v.so (raises if it has not been built).
+
+    torch is imported first: its HIP runtime carries the same soname as the
+    one libsg2v.so was linked against, so the dynamic loader binds libsg2v.so
+    to torch's runtime and torch's streams and device pointers are valid in
+    the library.  Loading libsg2v.so first would pull a second HIP runtime
+    into the process."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing; build it with "
                               "`python -m paper_2009_11665_amd.build`")
+        import torch  # noqa: F401  (binds the HIP runtime, see above)
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                  ctypes.c_uint64)

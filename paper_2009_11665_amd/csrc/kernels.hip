@@ -168,47 +168,50 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
         if constexpr (WEIGHTED)
           my_w = __builtin_bit_cast(float, __builtin_amdgcn_ds_permute(dst << 2, __builtin_bit_cast(int, my_w)));
       }
-      int s = stream;
-      for (; s + 3 * streams < cnt; s += 4 * streams) {
-        const int j0 = shfl_i32(my_j, gbase + s);
-        const int j1 = shfl_i32(my_j, gbase + s + streams);
-        const int j2 = shfl_i32(my_j, gbase + s + 2 * streams);
-        const int j3 = shfl_i32(my_j, gbase + s + 3 * streams);
-        const V16<T> v0 = *(const V16<T> *)(M + (int64_t)j0 * a.ldm + col0);
-        const V16<T> v1 = *(const V16<T> *)(M + (int64_t)j1 * a.ldm + col0);
-        const V16<T> v2 = *(const V16<T> *)(M + (int64_t)j2 * a.ldm + col0);
-        const V16<T> v3 = *(const V16<T> *)(M + (int64_t)j3 * a.ldm + col0);
-        if constexpr (WEIGHTED) {
-          const T w0 = (T)shfl(my_w, gbase + s), w1 = (T)shfl(my_w, gbase + s + streams);
-          const T w2 = (T)shfl(my_w, gbase + s + 2 * streams);
-          const T w3 = (T)shfl(my_w, gbase + s + 3 * streams);
+      // Every lane of the task's group runs the same iterations (cnt is
+      // uniform within the group), so each ds_bpermute reads an active lane;
+      // slots past cnt load nothing and add zero.
+      for (int t0 = 0; t0 < cnt; t0 += 4 * streams) {
+        int jq[4];
+        bool ok[4];
 #pragma unroll
-          for (int u = 0; u < N; ++u) {
-            acc0.x[u] = A::fma(w0, v0.x[u], acc0.x[u], ovf);
-            acc1.x[u] = A::fma(w1, v1.x[u], acc1.x[u], ovf);
-            acc2.x[u] = A::fma(w2, v2.x[u], acc2.x[u], ovf);
-            acc3.x[u] = A::fma(w3, v3.x[u], acc3.x[u], ovf);
-          }
-        } else {
+        for (int q = 0; q < 4; ++q) {
+          const int sq = t0 + stream + q * streams;
+          ok[q] = sq < cnt;
+          jq[q] = shfl_i32(my_j, gbase + (ok[q] ? sq : 0));
+        }
+        V16<T> v[4];
 #pragma unroll
-          for (int u = 0; u < N; ++u) {
-            acc0.x[u] = A::add(acc0.x[u], v0.x[u], ovf);
-            acc1.x[u] = A::add(acc1.x[u], v1.x[u], ovf);
-            acc2.x[u] = A::add(acc2.x[u], v2.x[u], ovf);
-            acc3.x[u] = A::add(acc3.x[u], v3.x[u], ovf);
+        for (int q = 0; q < 4; ++q) {
+          if (ok[q]) {
+            v[q] = *(const V16<T> *)(M + (int64_t)jq[q] * a.ldm + col0);
+          } else {
+#pragma unroll
+            for (int u = 0; u < N; ++u) v[q].x[u] = T(0);
           }
         }
-      }
-      for (; s < cnt; s += streams) {
-        const int j0 = shfl_i32(my_j, gbase + s);
-        const V16<T> v0 = *(const V16<T> *)(M + (int64_t)j0 * a.ldm + col0);
         if constexpr (WEIGHTED) {
-          const T w0 = (T)shfl(my_w, gbase + s);
+          T wq[4];
 #pragma unroll
-          for (int u = 0; u < N; ++u) acc0.x[u] = A::fma(w0, v0.x[u], acc0.x[u], ovf);
+          for (int q = 0; q < 4; ++q) {
+            const int sq = t0 + stream + q * streams;
+            wq[q] = (T)shfl(my_w, gbase + (ok[q] ? sq : 0));
+          }
+#pragma unroll
+          for (int u = 0; u < N; ++u) {
+            acc0.x[u] = A::fma(wq[0], v[0].x[u], acc0.x[u], ovf);
+            acc1.x[u] = A::fma(wq[1], v[1].x[u], acc1.x[u], ovf);
+            acc2.x[u] = A::fma(wq[2], v[2].x[u], acc2.x[u], ovf);
+            acc3.x[u] = A::fma(wq[3], v[3].x[u], acc3.x[u], ovf);
+          }
         } else {
 #pragma unroll
-          for (int u = 0; u < N; ++u) acc0.x[u] = A::add(acc0.x[u], v0.x[u], ovf);
+          for (int u = 0; u < N; ++u) {
+            acc0.x[u] = A::add(acc0.x[u], v[0].x[u], ovf);
+            acc1.x[u] = A::add(acc1.x[u], v[1].x[u], ovf);
+            acc2.x[u] = A::add(acc2.x[u], v[2].x[u], ovf);
+            acc3.x[u] = A::add(acc3.x[u], v[3].x[u], ovf);
+          }
         }
       }
     }
