@@ -235,8 +235,10 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
 /* Tuning knobs (0 = automatic).  spmm_width: columns per SpMM chunk;
  * ema_rows: rows per eMA tile; batch: colourings per pass; flags:
  * SG2V_TUNE_NO_COLOR_SKIP disables the colour-based skipping of SpMM row
- * segments; budget_bytes: device memory the count may use. */
+ * segments, SG2V_TUNE_NO_COLOR_EMA the colour-restricted multiply-add
+ * (vertices grouped by colour); budget_bytes: device memory the count may use. */
 #define SG2V_TUNE_NO_COLOR_SKIP 1
+#define SG2V_TUNE_NO_COLOR_EMA 2
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;

@@ -46,6 +46,18 @@ struct Node {
   int np_tp = 0;               // pairs per passive column = C(k - size_p, size_a)
   std::vector<int32_t> tr_p;   // [cols_p][np_tp] x (I_s, I_a): output sets containing I_p
   std::vector<int32_t> add;    // active child is one vertex: [k][cols_p] -> rank(P + {c}) or -1
+  // colour-restricted multiply-add (general splits): a vertex of colour c has
+  // M_s(i, C) = 0 unless c is in C, and only pairs whose active set holds c
+  // contribute.  Per colour c (all sizes are equal across colours):
+  //   ca[c][*]  active columns holding c      (Sa = C(k-1, |T_a|-1))
+  //   cb[c][*]  passive columns not holding c (Sb = C(k-1, |T_p|))
+  //   co[c][*]  output columns holding c      (U  = C(k-1, |T_s|-1))
+  //   cz[c][*]  output columns not holding c  (Z  = C(k-1, |T_s|))
+  //   cp[c][q][u] = position in ca | position in cb << 16, q < Q = C(|T_s|-1, |T_a|-1)
+  int64_t c_sa = 0, c_sb = 0, c_u = 0, c_z = 0;
+  int c_q = 0;
+  std::vector<int32_t> ca, cb, co, cz;
+  std::vector<uint32_t> cp;
 };
 
 enum RootKind {
@@ -78,7 +90,9 @@ struct Plan {
     int device = -1;
     std::vector<void *> pairs, drop;  // per node
     std::vector<void *> tr_a, tr_p, add;
+    std::vector<void *> cpr;  // colour-restricted tables, one block per node
     void *root_list = nullptr;
+    void *root_list16 = nullptr;  // (x | y << 16), when every index fits 16 bits
     // SpMM colour-skip masks per (node, colourings per pass, chunk width)
     std::map<std::tuple<int, int, int>, void *> chunks;
   };

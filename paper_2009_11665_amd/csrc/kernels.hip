@@ -83,7 +83,8 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
 }
 
 // ===========================================================================
-// Neighbour aggregation B = A_G M_p (Sec. 4.1, Alg. 4; Alg. 5 lines 7-9) as a
+// BEGIN k_spmm
+// Neighbour aggregation B = A_G M_p (Sec. 4.1, Alg. 4; the SpMV step of Alg. 5) as a
 // CSR SpMM over one column chunk of W = G * N columns per blockIdx.y.
 //
 // Rows are cut into tasks of at most a fixed number of neighbours (long rows
@@ -311,8 +312,9 @@ __global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
   }
 }
 
+// END k_spmm
 // ===========================================================================
-// Count combination, general split (Alg. 3 stage 2; Alg. 5 lines 10-13):
+// Count combination, general split (Alg. 3 stage 2; the eMA step of Alg. 5):
 //   M_s(i, C) = sum over pairs (I_a, I_p) of C of M_a(i, I_a) * B(i, I_p).
 // A block stages R rows of M_a and B (one colouring, blockIdx.y) in LDS --
 // scaled to a common exponent in FP32S mode -- then each thread owns output
@@ -415,6 +417,151 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
     __syncthreads();
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
       if (lmx[c] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + c, __float_as_uint(lmx[c]));
+      if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
+    }
+  }
+}
+
+// Rows grouped by colour for the colour-restricted multiply-add.
+__global__ void k_bucket_count(const uint8_t *colors, int64_t n, int32_t j0, int32_t k,
+                               int32_t *counts) {
+  __shared__ int h[32];
+  const int j = blockIdx.y;
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint8_t *col = colors + (int64_t)(j0 + j) * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&h[col[i]], 1);
+  __syncthreads();
+  if (threadIdx.x < k && h[threadIdx.x]) atomicAdd(&counts[j * k + threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_bucket_scatter(const uint8_t *colors, int64_t n, int32_t j0, int32_t k,
+                                 const int32_t *counts, int32_t *cursor, int32_t *perm) {
+  __shared__ int off[32];
+  const int j = blockIdx.y;
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int c = 0; c < k; ++c) {
+      off[c] = acc;
+      acc += counts[j * k + c];
+    }
+  }
+  __syncthreads();
+  const uint8_t *col = colors + (int64_t)(j0 + j) * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = col[i];
+    const int pos = atomicAdd(&cursor[j * k + c], 1);
+    perm[(int64_t)j * n + off[c] + pos] = (int32_t)i;
+  }
+}
+
+// Colour-restricted multiply-add.  For a vertex of colour c, M_a(i, S) = 0
+// unless c is in S (the active child's root is i), so M_s(i, C) = 0 for C
+// without c and only pairs whose active set holds c contribute.  A block
+// takes R rows of one colour (rows grouped by colour), stages the active
+// columns holding c and the passive columns without c in LDS, and each thread
+// owns output columns holding c; the other output columns are written as 0.
+template <typename T, int R, bool SCALED>
+__global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
+  using A = Arith<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int rows[R];
+  const int j = blockIdx.y;
+  const int sa = a.Sa | 1, sb = a.Sb | 1;
+  T *la = (T *)smem;
+  T *lb = la + R * sa;
+  unsigned *lmx = (unsigned *)(lb + R * sb);
+  const T *Ma = (const T *)a.Ma;
+  const T *Bt = (const T *)a.B;
+  T *Ms = (T *)a.Ms;
+  const float *fa = SCALED ? a.fa + (int64_t)j * a.Ca : nullptr;
+  const float *fb = SCALED ? a.fb + (int64_t)j * a.Cb : nullptr;
+  const int32_t *cnt = a.counts + (int64_t)j * a.k;
+  bool ovf = false;
+  if (SCALED)
+    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0u;
+  int64_t ntiles = 0;
+  for (int c = 0; c < a.k; ++c) ntiles += (cnt[c] + R - 1) / R;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // colour and first row of this tile
+    int c = 0;
+    int64_t acc_t = 0, off = 0;
+    for (; c < a.k; ++c) {
+      const int64_t tc = (cnt[c] + R - 1) / R;
+      if (t < acc_t + tc) break;
+      acc_t += tc;
+      off += cnt[c];
+    }
+    const int64_t first = (t - acc_t) * R;
+    const int nrow = (int)min<int64_t>(R, cnt[c] - first);
+    __syncthreads();
+    if (threadIdx.x < R)
+      rows[threadIdx.x] = threadIdx.x < nrow ? a.perm[(int64_t)j * a.n + off + first + threadIdx.x] : -1;
+    __syncthreads();
+    const int32_t *ca = a.ca + (int64_t)c * a.Sa;
+    const int32_t *cb = a.cb + (int64_t)c * a.Sb;
+    for (int x = threadIdx.x; x < R * a.Sa; x += BLOCK) {
+      const int r = x / a.Sa, q = x - r * a.Sa;
+      T v = T(0);
+      if (rows[r] >= 0) {
+        const int col = ca[q];
+        v = Ma[(int64_t)rows[r] * a.lda + (int64_t)j * a.Ca + col];
+        if constexpr (SCALED) v *= fa[col];
+      }
+      la[r * sa + q] = v;
+    }
+    for (int x = threadIdx.x; x < R * a.Sb; x += BLOCK) {
+      const int r = x / a.Sb, q = x - r * a.Sb;
+      T v = T(0);
+      if (rows[r] >= 0) {
+        const int col = cb[q];
+        v = Bt[(int64_t)rows[r] * a.ldb + (int64_t)j * a.Cb + col];
+        if constexpr (SCALED) v *= fb[col];
+      }
+      lb[r * sb + q] = v;
+    }
+    __syncthreads();
+    const uint32_t *cp = a.cp + (int64_t)c * a.Q * a.U;
+    const int32_t *co = a.co + (int64_t)c * a.U;
+    for (int u = threadIdx.x; u < a.U; u += BLOCK) {
+      T acc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = T(0);
+      for (int q = 0; q < a.Q; ++q) {
+        const uint32_t p = cp[(int64_t)q * a.U + u];
+        const int x = p & 0xFFFFu, y = p >> 16;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + x], lb[r * sb + y], acc[r], ovf);
+      }
+      const int C = co[u];
+      float m = 0.f;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (rows[r] >= 0) {
+          Ms[(int64_t)rows[r] * a.lds + (int64_t)j * a.Cs + C] = acc[r];
+          if constexpr (SCALED) m = fmaxf(m, (float)acc[r]);
+        }
+      }
+      if constexpr (SCALED) {
+        if (m > 0.f) atomicMax(&lmx[C], __float_as_uint(m));
+      }
+    }
+    const int32_t *cz = a.cz + (int64_t)c * a.Z;
+    for (int x = threadIdx.x; x < R * a.Z; x += BLOCK) {
+      const int r = x / a.Z, v = x - r * a.Z;
+      if (rows[r] >= 0) Ms[(int64_t)rows[r] * a.lds + (int64_t)j * a.Cs + cz[v]] = T(0);
+    }
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+  if constexpr (SCALED) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
+      if (lmx[c]) atomicMax(a.mx + (int64_t)j * a.Cs + c, lmx[c]);
       if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
     }
   }
@@ -529,6 +676,69 @@ __global__ void __launch_bounds__(BLOCK) k_root(RootArgs a) {
     }
     ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = b;
   }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+}
+
+// Root reduction with the vertex's rows staged in LDS (multiplied by the
+// column factors in FP32S): one block per row at a time, threads stride over
+// the colour's list, a fixed-order reduction gives the row value, which is
+// accumulated over the block's rows in double (uint64 in U64).
+template <typename T, bool SCALED, bool HASY>
+__global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
+  using A = Arith<T>;
+  using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ T red[WAVES_PER_BLOCK];
+  T *lx = (T *)smem;
+  T *ly = (HASY && !a.same_xy) ? lx + a.Cx : lx;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int j = blockIdx.y;
+  const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
+  const T *X = (const T *)a.X;
+  const T *Y = (const T *)a.Y;
+  const float *fx = SCALED ? a.fx + (int64_t)j * a.Cx : nullptr;
+  const float *fy = (SCALED && HASY) ? a.fy + (int64_t)j * a.Cy : nullptr;
+  bool ovf = false;
+  Acc tot = Acc(0);
+  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    __syncthreads();
+    const T *xr = X + i * a.ldx + (int64_t)j * a.Cx;
+    for (int c = threadIdx.x; c < a.Cx; c += BLOCK) {
+      T v = xr[c];
+      if constexpr (SCALED) v *= fx[c];
+      lx[c] = v;
+    }
+    if (HASY && !a.same_xy) {
+      const T *yr = Y + i * a.ldy + (int64_t)j * a.Cy;
+      for (int c = threadIdx.x; c < a.Cy; c += BLOCK) {
+        T v = yr[c];
+        if constexpr (SCALED) v *= fy[c];
+        ly[c] = v;
+      }
+    }
+    __syncthreads();
+    const int c = col[i];
+    const uint32_t *lc = a.list16 + (int64_t)c * a.L;
+    T s = T(0);
+    for (int64_t q = threadIdx.x; q < a.L; q += BLOCK) {
+      const uint32_t p = lc[q];
+      if constexpr (HASY) s = A::fma(lx[p & 0xFFFFu], ly[p >> 16], s, ovf);
+      else s = A::add(s, lx[p & 0xFFFFu], ovf);
+    }
+    for (int off = 1; off < WAVE; off <<= 1) s = A::add(s, shfl_xor(s, off), ovf);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T r = red[0];
+      for (int q = 1; q < WAVES_PER_BLOCK; ++q) r = A::add(r, red[q], ovf);
+      if constexpr (is_u64<Acc>) tot = A::add(tot, r, ovf);
+      else tot += (double)r;
+    }
+  }
+  if (threadIdx.x == 0) ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = tot;
   if constexpr (is_u64<T>) {
     if (ovf) atomicOr(a.ovf, 1);
   }
@@ -765,12 +975,57 @@ void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) {
   }
 }
 
+template <typename T, bool SC>
+static void root_lds_t(const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+  auto k1 = k_root_lds<T, SC, true>;
+  auto k0 = k_root_lds<T, SC, false>;
+  auto kern = a.Y ? k1 : k0;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kern<<<grid, BLOCK, lds, s>>>(a);
+}
+
+void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+  if (dtype == DT_F32) root_lds_t<float, true>(a, grid, lds, s);
+  else if (dtype == DT_F64) root_lds_t<double, false>(a, grid, lds, s);
+  else root_lds_t<uint64_t, false>(a, grid, lds, s);
+}
+
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s) {
   if (dtype == DT_U64)
     k_root_final<uint64_t><<<1, 64, 0, s>>>((const uint64_t *)partial, nblk, b, (uint64_t *)out, ovf);
   else
     k_root_final<double><<<1, 64, 0, s>>>((const double *)partial, nblk, b, (double *)out, ovf);
+}
+
+void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int32_t k, int32_t *counts,
+                   int32_t *cursor, int32_t *perm, hipStream_t s) {
+  const unsigned g = grid_cap((n + BLOCK - 1) / BLOCK, 1024);
+  k_fill_u32<<<grid_cap((2 * b * k + BLOCK - 1) / BLOCK, 64), BLOCK, 0, s>>>((unsigned *)counts, (int64_t)b * k, 0u);
+  k_fill_u32<<<grid_cap((2 * b * k + BLOCK - 1) / BLOCK, 64), BLOCK, 0, s>>>((unsigned *)cursor, (int64_t)b * k, 0u);
+  k_bucket_count<<<dim3(g, b), BLOCK, 0, s>>>(colors, n, j0, k, counts);
+  k_bucket_scatter<<<dim3(g, b), BLOCK, 0, s>>>(colors, n, j0, k, counts, cursor, perm);
+}
+
+template <typename T, bool SC>
+static int ema_colour_t(const EmaColourArgs &a, int R, dim3 grid, size_t lds, hipStream_t s) {
+  auto go = [&](auto kern) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    kern<<<grid, BLOCK, lds, s>>>(a);
+  };
+  switch (R) {
+    case 2: go(k_ema_colour<T, 2, SC>); return 0;
+    case 4: go(k_ema_colour<T, 4, SC>); return 0;
+    case 8: go(k_ema_colour<T, 8, SC>); return 0;
+    case 16: go(k_ema_colour<T, 16, SC>); return 0;
+    default: return -1;
+  }
+}
+
+int launch_ema_colour(int dtype, const EmaColourArgs &a, int R, dim3 grid, size_t lds, hipStream_t s) {
+  if (dtype == DT_F32) return ema_colour_t<float, true>(a, R, grid, lds, s);
+  if (dtype == DT_F64) return ema_colour_t<double, false>(a, R, grid, lds, s);
+  return ema_colour_t<uint64_t, false>(a, R, grid, lds, s);
 }
 
 void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,

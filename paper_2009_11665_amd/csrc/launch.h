@@ -89,6 +89,35 @@ struct EmaArgs {
   int32_t accumulate;    // general kernel: 1 adds into Ms (adjoint)
 };
 
+// colour-restricted multiply-add (rows bucketed by colour)
+struct EmaColourArgs {
+  const void *Ma;
+  int64_t lda;
+  int32_t Ca;
+  const void *B;
+  int64_t ldb;
+  int32_t Cb;
+  void *Ms;
+  int64_t lds;
+  int32_t Cs;
+  const int32_t *ca, *cb, *co, *cz;  // [k][Sa], [k][Sb], [k][U], [k][Z]
+  const uint32_t *cp;                // [k][Q][U]
+  int32_t Sa, Sb, U, Z, Q, k;
+  const int32_t *perm;    // [b][n] rows grouped by colour
+  const int32_t *counts;  // [b][k] rows per colour
+  int64_t n;
+  const float *fa, *fb;
+  const int *Ea, *Eb;
+  unsigned *mx;
+  int *es;
+  int *ovf;
+};
+
+// rows grouped by colour: counts[j][c], then perm[j][.] (order within a colour is arbitrary)
+void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int32_t k, int32_t *counts,
+                   int32_t *cursor, int32_t *perm, hipStream_t s);
+int launch_ema_colour(int dtype, const EmaColourArgs &a, int R, dim3 grid, size_t lds, hipStream_t s);
+
 // edge gradient: grad[e] += sum_c Bbar(i, c) * M_p(j, c) for e = (i -> j)
 struct SddmmArgs {
   const int64_t *row_ptr;
@@ -119,6 +148,8 @@ struct RootArgs {
   const float *fx, *fy;
   void *partial;  // [b][gridDim.x] double or uint64
   int *ovf;
+  const uint32_t *list16;  // nullable: (x | y << 16) [k][L], y = 0xFFFF for Y = 1
+  int32_t same_xy;         // X and Y are the same table (staged once)
 };
 
 void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
@@ -130,6 +161,8 @@ int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid
                        hipStream_t s);
 void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s);
 void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
+// block per vertex row, rows staged in LDS; lds = bytes of the staged rows
+void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s);
 void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,

@@ -299,6 +299,65 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
     }
   }
 
+  // Colour-restricted tables of general splits (active child with more than
+  // one vertex), built when every compact position fits 16 bits.
+  for (auto &nd : P->nodes) {
+    if (nd.size == 1) continue;
+    const Node &A = P->nodes[nd.active];
+    const Node &Pn = P->nodes[nd.passive];
+    if (A.size == 1) continue;
+    const int m = nd.size, ma = A.size, mp = Pn.size;
+    nd.c_sa = binom(k - 1, ma - 1);
+    nd.c_sb = binom(k - 1, mp);
+    nd.c_u = binom(k - 1, m - 1);
+    nd.c_z = binom(k - 1, m);
+    nd.c_q = (int)binom(m - 1, ma - 1);
+    if (nd.c_sa >= 0xFFFF || nd.c_sb >= 0xFFFF) {
+      nd.c_q = 0;
+      continue;
+    }
+    const int64_t ca_cols = binom(k, ma), cb_cols = binom(k, mp);
+    nd.ca.resize((size_t)k * nd.c_sa);
+    nd.cb.resize((size_t)k * nd.c_sb);
+    nd.co.resize((size_t)k * nd.c_u);
+    nd.cz.resize((size_t)k * nd.c_z);
+    nd.cp.resize((size_t)k * nd.c_q * nd.c_u);
+    std::vector<int32_t> posa(ca_cols), posb(cb_cols);
+    for (int c = 0; c < k; ++c) {
+      int64_t na = 0, nb = 0, nu = 0, nz = 0;
+      for (int64_t r = 0; r < ca_cols; ++r) {
+        posa[r] = -1;
+        if (colex_unrank(r, ma, k) >> c & 1u) {
+          posa[r] = (int32_t)na;
+          nd.ca[(size_t)c * nd.c_sa + na++] = (int32_t)r;
+        }
+      }
+      for (int64_t r = 0; r < cb_cols; ++r) {
+        posb[r] = -1;
+        if (!(colex_unrank(r, mp, k) >> c & 1u)) {
+          posb[r] = (int32_t)nb;
+          nd.cb[(size_t)c * nd.c_sb + nb++] = (int32_t)r;
+        }
+      }
+      for (int64_t r = 0; r < nd.cols; ++r) {
+        if (!(colex_unrank(r, m, k) >> c & 1u)) {
+          nd.cz[(size_t)c * nd.c_z + nz++] = (int32_t)r;
+          continue;
+        }
+        const int64_t u = nu++;
+        nd.co[(size_t)c * nd.c_u + u] = (int32_t)r;
+        int q = 0;
+        for (int t = 0; t < nd.np; ++t) {
+          const int32_t ia = nd.pairs[((size_t)r * nd.np + t) * 2 + 0];
+          const int32_t ip = nd.pairs[((size_t)r * nd.np + t) * 2 + 1];
+          if (posa[ia] < 0) continue;  // active set without c: M_a(i, .) = 0
+          nd.cp[((size_t)c * nd.c_q + q) * nd.c_u + u] = (uint32_t)posa[ia] | ((uint32_t)posb[ip] << 16);
+          ++q;
+        }
+      }
+    }
+  }
+
   // Root reduction lists.
   P->fused.assign(P->nodes.size(), 0);
   const Node &R = P->nodes[P->root];

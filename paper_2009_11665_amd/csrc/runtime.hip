@@ -465,6 +465,8 @@ struct DevPlan {
   std::vector<int32_t *> pairs, drop;  // per node, device
   std::vector<int32_t *> tr_a, tr_p, add;
   int32_t *root_list = nullptr;
+  uint32_t *root_list16 = nullptr;
+  std::vector<char *> cpr;  // colour-restricted tables per node
 };
 
 // pair-major copy ([q][col]) of a [col][np] x 2 table
@@ -494,6 +496,9 @@ void fill_devplan(const Plan::DeviceTables &d, DevPlan *out) {
     out->add[i] = (int32_t *)d.add[i];
   }
   out->root_list = (int32_t *)d.root_list;
+  out->root_list16 = (uint32_t *)d.root_list16;
+  out->cpr.assign(nn, nullptr);
+  for (size_t i = 0; i < nn && i < d.cpr.size(); ++i) out->cpr[i] = (char *)d.cpr[i];
 }
 
 sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) {
@@ -523,7 +528,29 @@ sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) 
     if (!nd.drop.empty()) ST_TRY(upload(nd.drop, &D.drop[i], s));
     if (!nd.add.empty()) ST_TRY(upload(nd.add, &D.add[i], s));
   }
-  if (!P.root_list.empty()) ST_TRY(upload(P.root_list, &D.root_list, s));
+  D.cpr.assign(nn, nullptr);
+  for (size_t i = 0; i < nn; ++i) {
+    const Node &nd = P.nodes[i];
+    if (nd.c_q == 0) continue;
+    std::vector<uint32_t> blk;
+    blk.insert(blk.end(), nd.ca.begin(), nd.ca.end());
+    blk.insert(blk.end(), nd.cb.begin(), nd.cb.end());
+    blk.insert(blk.end(), nd.co.begin(), nd.co.end());
+    blk.insert(blk.end(), nd.cz.begin(), nd.cz.end());
+    blk.insert(blk.end(), nd.cp.begin(), nd.cp.end());
+    ST_TRY(upload(blk, &D.cpr[i], s));
+  }
+  if (!P.root_list.empty()) {
+    ST_TRY(upload(P.root_list, &D.root_list, s));
+    bool fits = true;
+    std::vector<uint32_t> l16(P.root_list.size() / 2);
+    for (size_t q = 0; q < l16.size(); ++q) {
+      const int32_t x = P.root_list[2 * q], y = P.root_list[2 * q + 1];
+      fits &= x >= 0 && x < 0xFFFF && y >= -1 && y < 0xFFFF;
+      l16[q] = (uint32_t)x | ((uint32_t)(y < 0 ? 0xFFFF : y) << 16);
+    }
+    if (fits) ST_TRY(upload(l16, &D.root_list16, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   P.dev.push_back(D);
   fill_devplan(P.dev.back(), out);
@@ -563,7 +590,7 @@ struct PassPlan {
 };
 
 struct Workspace {
-  DevBuf arena, small, partial, result, ovf, grad;
+  DevBuf arena, small, partial, result, ovf, grad, bucket;
 };
 
 Workspace &workspace() {
@@ -705,6 +732,8 @@ struct Ctx {
   int *ovf;
   int cu_count = 256;
   size_t lds_max = 65536;
+  int bucket_j0 = -1;  // pass whose colour buckets are in ws->bucket
+  int bucket_b = 0;
 };
 
 sg2v_status bind_tables(Ctx &x) {
@@ -914,6 +943,77 @@ sg2v_status launch_general(Ctx &x, EmaArgs &a) {
   return SG2V_OK;
 }
 
+// Colour-restricted multiply-add of a general split: vertices are grouped by
+// colour once per pass, then k_ema_colour works on tiles of one colour.
+sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
+  const Node &nd = x.P->nodes[node];
+  const int k = x.P->k;
+  int32_t *counts = (int32_t *)x.ws->bucket.p;
+  int32_t *cursor = counts + (size_t)x.b * 32;
+  int32_t *perm = cursor + (size_t)x.b * 32;
+  if (x.bucket_j0 != x.j0 || x.bucket_b != x.b) {
+    launch_bucket(x.c->d, x.g->n, x.j0, x.b, k, counts, cursor, perm, x.s);
+    x.bucket_j0 = x.j0;
+    x.bucket_b = x.b;
+  }
+  EmaColourArgs a;
+  a.Ma = g.Ma;
+  a.lda = g.lda;
+  a.Ca = g.Ca;
+  a.B = g.B;
+  a.ldb = g.ldb;
+  a.Cb = g.Cb;
+  a.Ms = g.Ms;
+  a.lds = g.lds;
+  a.Cs = g.Cs;
+  const int32_t *base = (const int32_t *)x.dp.cpr[node];
+  a.ca = base;
+  a.cb = a.ca + (size_t)k * nd.c_sa;
+  a.co = a.cb + (size_t)k * nd.c_sb;
+  a.cz = a.co + (size_t)k * nd.c_u;
+  a.cp = (const uint32_t *)(a.cz + (size_t)k * nd.c_z);
+  a.Sa = (int32_t)nd.c_sa;
+  a.Sb = (int32_t)nd.c_sb;
+  a.U = (int32_t)nd.c_u;
+  a.Z = (int32_t)nd.c_z;
+  a.Q = nd.c_q;
+  a.k = k;
+  a.perm = perm;
+  a.counts = counts;
+  a.n = x.g->n;
+  a.fa = g.fa;
+  a.fb = g.fb;
+  a.Ea = g.Ea;
+  a.Eb = g.Eb;
+  a.mx = g.mx;
+  a.es = g.es;
+  a.ovf = g.ovf;
+  const bool sc = x.dt == DT_F32;
+  const size_t lmx = sc ? (size_t)nd.cols * 4 : 0;
+  const size_t budget = std::min<size_t>(x.lds_max, 80 * 1024);
+  const size_t rowb = (size_t)((a.Sa | 1) + (a.Sb | 1)) * x.es;
+  sg2v_tuning_t tu = tuning();
+  int R = tu.ema_rows > 0 ? std::min(tu.ema_rows, 16) : 16;
+  while (R > 2 && R * rowb + lmx > budget) R /= 2;
+  if (R < 2) R = 2;
+  const size_t lds = R * rowb + lmx;
+  if (lds > x.lds_max) {
+    set_error("sg2v_count: colour-restricted eMA needs %zu bytes of LDS", lds);
+    return SG2V_ERANGE;
+  }
+  const int64_t ntiles = x.g->n / R + k;
+  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(x.lds_max / lds));
+  const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8));
+  ProfScope ps(SG2V_K_EMA_GENERAL,
+               (double)x.g->n * x.b * (double)(nd.cols + nd.c_sa + nd.c_sb) * x.es,
+               (double)x.g->n * x.b * (double)nd.c_u * nd.c_q, x.s);
+  if (launch_ema_colour(x.dt, a, R, dim3((unsigned)std::max<int64_t>(1, blocks), (unsigned)x.b), lds, x.s)) {
+    set_error("sg2v_count: no colour-restricted eMA variant for R=%d", R);
+    return SG2V_EINVAL;
+  }
+  return SG2V_OK;
+}
+
 sg2v_status step_ema(Ctx &x, int node, bool single) {
   const Plan &P = *x.P;
   const Node &nd = P.nodes[node];
@@ -964,10 +1064,14 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
       a.fa = Ma.f;
       a.Ea = Ma.E;
     }
-    ProfScope ps(SG2V_K_EMA_GENERAL,
-                 (double)x.g->n * x.b * (double)(nd.cols + Ma.cols + Bt.cols) * x.es,
-                 (double)x.g->n * x.b * (double)nd.cols * nd.np, x.s);
-    ST_TRY(launch_general(x, a));
+    if (nd.c_q > 0 && x.dp.cpr[node] && !(tuning().flags & SG2V_TUNE_NO_COLOR_EMA)) {
+      ST_TRY(ema_colour(x, node, a));
+    } else {
+      ProfScope ps(SG2V_K_EMA_GENERAL,
+                   (double)x.g->n * x.b * (double)(nd.cols + Ma.cols + Bt.cols) * x.es,
+                   (double)x.g->n * x.b * (double)nd.cols * nd.np, x.s);
+      ST_TRY(launch_general(x, a));
+    }
   }
   if (x.dt == DT_U64) launch_zero_pad(x.dt, Ms.p, x.g->n, Ms.ld, Ms.cols * x.b, x.s);
   norm(x, Ms);
@@ -1018,11 +1122,16 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const int nblk = 1024;
   a.partial = x.ws->partial.p;
   a.ovf = x.ovf;
+  a.list16 = x.dp.root_list16;
+  a.same_xy = Y && Y->p == X->p;
+  const size_t stage = (size_t)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es;
+  const bool use_lds = a.list16 && stage <= std::min<size_t>(x.lds_max, 64 * 1024);
   {
     ProfScope ps(SG2V_K_ROOT,
-                 (double)x.g->n * x.b * (double)(X->cols + (Y ? Y->cols : 0)) * x.es,
+                 (double)x.g->n * x.b * (double)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es,
                  (double)x.g->n * x.b * (double)P.root_L, x.s);
-    launch_root(x.dt, a, dim3(nblk, x.b), x.s);
+    if (use_lds) launch_root_lds(x.dt, a, dim3(nblk, x.b), stage, x.s);
+    else launch_root(x.dt, a, dim3(nblk, x.b), x.s);
   }
   const int es = 8;
   launch_root_final(x.dt, a.partial, nblk, x.b, (char *)result + (size_t)x.j0 * es, x.ovf, x.s);
@@ -1170,7 +1279,9 @@ sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_col
   ST_TRY(x.ws->small.ensure(x.pp.small_bytes));
   ST_TRY(x.ws->partial.ensure((size_t)1024 * b * 8));
   ST_TRY(x.ws->ovf.ensure(256));
+  ST_TRY(x.ws->bucket.ensure((size_t)b * (64 + g->n) * 4 + 256));
   x.ovf = (int *)x.ws->ovf.p;
+  x.bucket_j0 = -1;
   return bind_tables(x);
 }
 
@@ -1327,7 +1438,7 @@ struct BatchGraph {
   uint64_t seed = 0;
   int ncol = 0, mode = 0;
   sg2v_tuning_t tune{};
-  uint64_t gens[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t gens[7] = {0, 0, 0, 0, 0, 0, 0};
   std::vector<std::unique_ptr<sg2v_colorings>> cols;
   hipGraphExec_t exec = nullptr;
   int device = -1;
@@ -1351,6 +1462,7 @@ void ws_gens(Workspace &ws, uint64_t *out) {
   out[3] = ws.result.gen;
   out[4] = ws.ovf.gen;
   out[5] = ws.grad.gen;
+  out[6] = ws.bucket.gen;
 }
 
 }  // namespace
@@ -1417,13 +1529,13 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
   HIP_TRY(hipStreamSynchronize(us));
 
   // reuse a cached executable graph if every input and buffer is unchanged
-  uint64_t gens[6];
+  uint64_t gens[7];
   ws_gens(ws, gens);
   BatchGraph *hit = nullptr;
   for (auto &e : g_batch_cache) {
     if (e->g == g && e->seed == seed && e->ncol == ncol && e->mode == mode && e->device == dev &&
         e->plans == bg->plans && same_tuning(e->tune, bg->tune) &&
-        std::equal(gens, gens + 6, e->gens))
+        std::equal(gens, gens + 7, e->gens))
       hit = e.get();
   }
   char *res = (char *)ws.result.p;
@@ -1748,10 +1860,12 @@ extern "C" void sg2v_plan_destroy(sg2v_plan *plan) {
     for (void *q : d.pairs) (void)hipFree(q);
     for (void *q : d.drop) (void)hipFree(q);
     (void)hipFree(d.root_list);
+    (void)hipFree(d.root_list16);
     for (void *q : d.tr_a) (void)hipFree(q);
     for (void *q : d.tr_p) (void)hipFree(q);
     for (void *q : d.add) (void)hipFree(q);
     for (auto &kv : d.chunks) (void)hipFree(kv.second);
+    for (void *q : d.cpr) (void)hipFree(q);
     (void)hipSetDevice(cur);
   }
   delete plan;

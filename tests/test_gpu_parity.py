@@ -126,7 +126,7 @@ def test_intermediate_tables(small_rmat, mode, skip):
     (the only entries any multiply-add reads) and is zero elsewhere."""
     G = small_rmat
     old = sg.get_tuning()
-    sg.set_tuning(flags=0 if skip else sg.TUNE_NO_COLOR_SKIP)
+    sg.set_tuning(flags=0 if skip else (sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA))
     try:
         for par, k in ((gg.BINTREE7, 7), (gg.CATERPILLAR10, 10)):
             p = sg.Plan(par, k)
@@ -207,7 +207,8 @@ def test_spmm_widths_agree(small_rmat):
     old = sg.get_tuning()
     try:
         for w in (8, 16, 32, 64):
-            for fl in (0, sg.TUNE_NO_COLOR_SKIP):
+            for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA,
+                       sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA):
                 sg.set_tuning(spmm_width=w, flags=fl)
                 say("spmm width", w, "flags", fl)
                 got = sg.count(p, g, c, "u64")["colorful_u64"]
