@@ -239,6 +239,7 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
  * (vertices grouped by colour); budget_bytes: device memory the count may use. */
 #define SG2V_TUNE_NO_COLOR_SKIP 1
 #define SG2V_TUNE_NO_COLOR_EMA 2
+#define SG2V_TUNE_SPMM_UNROLL8 4 /* 8 row gathers in flight per SpMM stream instead of 4 */
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;

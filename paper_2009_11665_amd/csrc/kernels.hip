@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
 // The column maximum of B (FP32S) is reduced in registers, then across the
 // block in LDS, then one atomicMax per column per block.
 
-template <typename T, int G, bool WEIGHTED>
+template <typename T, int G, bool WEIGHTED, int UNR>
 __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
   constexpr int N = V16<T>::N;
   constexpr int W = G * N;
@@ -147,15 +147,26 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
 #pragma unroll
     for (int u = 0; u < N; ++u) acc0.x[u] = acc1.x[u] = acc2.x[u] = acc3.x[u] = T(0);
 
+    // neighbour indices (and colours) of the next block of lpt neighbours are
+    // loaded while the current block's rows are gathered
+    const uint8_t *ncol = colj ? a.nbr_col + (int64_t)jb * a.nnz + beg : nullptr;
+    int nx_j = 0, nx_c = 0;
+    float nx_w = 1.0f;
+    if (tl < len) {
+      nx_j = a.col_idx[beg + tl];
+      if constexpr (WEIGHTED) nx_w = a.w[beg + tl];
+      if (ncol) nx_c = ncol[tl];
+    }
     for (int base = 0; base < len; base += lpt) {
       const int e = base + tl;
-      int my_j = 0;
-      float my_w = 1.0f;
-      bool keep = false;
-      if (e < len) {
-        my_j = a.col_idx[beg + e];
-        if constexpr (WEIGHTED) my_w = a.w[beg + e];
-        keep = colj ? ((umask >> colj[my_j]) & 1u) != 0 : true;
+      int my_j = nx_j;
+      float my_w = nx_w;
+      const bool keep = e < len && (!ncol || ((umask >> nx_c) & 1u) != 0);
+      const int en = e + lpt;
+      if (en < len) {
+        nx_j = a.col_idx[beg + en];
+        if constexpr (WEIGHTED) nx_w = a.w[beg + en];
+        if (ncol) nx_c = ncol[en];
       }
       // compact the kept neighbours to the first lanes of the task's group,
       // preserving their order (a permutation of the group's lanes)
@@ -172,18 +183,18 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       // Every lane of the task's group runs the same iterations (cnt is
       // uniform within the group), so each ds_bpermute reads an active lane;
       // slots past cnt load nothing and add zero.
-      for (int t0 = 0; t0 < cnt; t0 += 4 * streams) {
-        int jq[4];
-        bool ok[4];
+      for (int t0 = 0; t0 < cnt; t0 += UNR * streams) {
+        int jq[UNR];
+        bool ok[UNR];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < UNR; ++q) {
           const int sq = t0 + stream + q * streams;
           ok[q] = sq < cnt;
           jq[q] = shfl_i32(my_j, gbase + (ok[q] ? sq : 0));
         }
-        V16<T> v[4];
+        V16<T> v[UNR];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < UNR; ++q) {
           if (ok[q]) {
             v[q] = *(const V16<T> *)(M + (int64_t)jq[q] * a.ldm + col0);
           } else {
@@ -191,27 +202,30 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
             for (int u = 0; u < N; ++u) v[q].x[u] = T(0);
           }
         }
-        if constexpr (WEIGHTED) {
-          T wq[4];
+        T wq[UNR];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < UNR; ++q) {
+          wq[q] = T(1);
+          if constexpr (WEIGHTED) {
             const int sq = t0 + stream + q * streams;
             wq[q] = (T)shfl(my_w, gbase + (ok[q] ? sq : 0));
           }
+        }
+#pragma unroll
+        for (int q = 0; q < UNR; q += 4) {
 #pragma unroll
           for (int u = 0; u < N; ++u) {
-            acc0.x[u] = A::fma(wq[0], v[0].x[u], acc0.x[u], ovf);
-            acc1.x[u] = A::fma(wq[1], v[1].x[u], acc1.x[u], ovf);
-            acc2.x[u] = A::fma(wq[2], v[2].x[u], acc2.x[u], ovf);
-            acc3.x[u] = A::fma(wq[3], v[3].x[u], acc3.x[u], ovf);
-          }
-        } else {
-#pragma unroll
-          for (int u = 0; u < N; ++u) {
-            acc0.x[u] = A::add(acc0.x[u], v[0].x[u], ovf);
-            acc1.x[u] = A::add(acc1.x[u], v[1].x[u], ovf);
-            acc2.x[u] = A::add(acc2.x[u], v[2].x[u], ovf);
-            acc3.x[u] = A::add(acc3.x[u], v[3].x[u], ovf);
+            if constexpr (WEIGHTED) {
+              acc0.x[u] = A::fma(wq[q + 0], v[q + 0].x[u], acc0.x[u], ovf);
+              acc1.x[u] = A::fma(wq[q + 1], v[q + 1].x[u], acc1.x[u], ovf);
+              acc2.x[u] = A::fma(wq[q + 2], v[q + 2].x[u], acc2.x[u], ovf);
+              acc3.x[u] = A::fma(wq[q + 3], v[q + 3].x[u], acc3.x[u], ovf);
+            } else {
+              acc0.x[u] = A::add(acc0.x[u], v[q + 0].x[u], ovf);
+              acc1.x[u] = A::add(acc1.x[u], v[q + 1].x[u], ovf);
+              acc2.x[u] = A::add(acc2.x[u], v[q + 2].x[u], ovf);
+              acc3.x[u] = A::add(acc3.x[u], v[q + 3].x[u], ovf);
+            }
           }
         }
       }
@@ -420,6 +434,18 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
       if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
     }
   }
+}
+
+// Colour of every CSR entry's neighbour, per colouring of the pass, so that
+// the SpMM reads it alongside col_idx instead of gathering it.
+__global__ void k_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *colors,
+                             int64_t n, int32_t j0, uint8_t *nbr) {
+  const int jj = blockIdx.y;
+  const uint8_t *col = colors + (int64_t)(j0 + jj) * n;
+  uint8_t *out = nbr + (int64_t)jj * nnz;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = col[col_idx[e]];
 }
 
 // Rows grouped by colour for the colour-restricted multiply-add.
@@ -885,27 +911,32 @@ void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s) {
   else hist_dispatch<uint64_t>(a, blocks, s);
 }
 
-template <typename T, int G>
+template <typename T, int G, int UNR>
 static void spmm_g(const SpmmArgs &a, dim3 grid, hipStream_t s) {
-  if (a.w) k_spmm<T, G, true><<<grid, BLOCK, 0, s>>>(a);
-  else k_spmm<T, G, false><<<grid, BLOCK, 0, s>>>(a);
+  if (a.w) k_spmm<T, G, true, UNR><<<grid, BLOCK, 0, s>>>(a);
+  else k_spmm<T, G, false, UNR><<<grid, BLOCK, 0, s>>>(a);
 }
 
-template <typename T>
+template <typename T, int UNR>
 static int spmm_t(const SpmmArgs &a, int G, dim3 grid, hipStream_t s) {
   switch (G) {
-    case 2: spmm_g<T, 2>(a, grid, s); return 0;
-    case 4: spmm_g<T, 4>(a, grid, s); return 0;
-    case 8: spmm_g<T, 8>(a, grid, s); return 0;
-    case 16: spmm_g<T, 16>(a, grid, s); return 0;
+    case 2: spmm_g<T, 2, UNR>(a, grid, s); return 0;
+    case 4: spmm_g<T, 4, UNR>(a, grid, s); return 0;
+    case 8: spmm_g<T, 8, UNR>(a, grid, s); return 0;
+    case 16: spmm_g<T, 16, UNR>(a, grid, s); return 0;
     default: return -1;
   }
 }
 
-int launch_spmm(int dtype, const SpmmArgs &a, int G, dim3 grid, hipStream_t s) {
-  if (dtype == DT_F32) return spmm_t<float>(a, G, grid, s);
-  if (dtype == DT_F64) return spmm_t<double>(a, G, grid, s);
-  return spmm_t<uint64_t>(a, G, grid, s);
+int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipStream_t s) {
+  if (unroll == 8) {
+    if (dtype == DT_F32) return spmm_t<float, 8>(a, G, grid, s);
+    if (dtype == DT_F64) return spmm_t<double, 8>(a, G, grid, s);
+    return spmm_t<uint64_t, 8>(a, G, grid, s);
+  }
+  if (dtype == DT_F32) return spmm_t<float, 4>(a, G, grid, s);
+  if (dtype == DT_F64) return spmm_t<double, 4>(a, G, grid, s);
+  return spmm_t<uint64_t, 4>(a, G, grid, s);
 }
 
 void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s) {
@@ -996,6 +1027,12 @@ void launch_root_final(int dtype, const void *partial, int nblk, int b, void *ou
     k_root_final<uint64_t><<<1, 64, 0, s>>>((const uint64_t *)partial, nblk, b, (uint64_t *)out, ovf);
   else
     k_root_final<double><<<1, 64, 0, s>>>((const double *)partial, nblk, b, (double *)out, ovf);
+}
+
+void launch_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *colors, int64_t n,
+                       int32_t j0, int32_t b, uint8_t *nbr, hipStream_t s) {
+  if (nnz == 0) return;
+  k_nbr_colors<<<dim3(grid_cap((nnz + BLOCK - 1) / BLOCK, 16384), b), BLOCK, 0, s>>>(col_idx, nnz, colors, n, j0, nbr);
 }
 
 void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int32_t k, int32_t *counts,

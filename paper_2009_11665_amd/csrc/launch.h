@@ -52,6 +52,8 @@ struct SpmmArgs {
   const uint8_t *colors;
   int32_t j0;
   int64_t n;
+  const uint8_t *nbr_col;  // [b][nnz] colour of col_idx[e] in each colouring of the pass
+  int64_t nnz;
 };
 
 struct CombineArgs {
@@ -113,6 +115,9 @@ struct EmaColourArgs {
   int *ovf;
 };
 
+// nbr[jj][e] = colour of col_idx[e] in colouring j0 + jj
+void launch_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *colors, int64_t n,
+                       int32_t j0, int32_t b, uint8_t *nbr, hipStream_t s);
 // rows grouped by colour: counts[j][c], then perm[j][.] (order within a colour is arbitrary)
 void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int32_t k, int32_t *counts,
                    int32_t *cursor, int32_t *perm, hipStream_t s);
@@ -155,7 +160,8 @@ struct RootArgs {
 void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
                   int32_t count, hipStream_t s);
 void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s);
-int launch_spmm(int dtype, const SpmmArgs &a, int G, dim3 grid, hipStream_t s);
+// unroll: gathers in flight per stream (4 or 8)
+int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipStream_t s);
 void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s);
 int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
                        hipStream_t s);

@@ -590,7 +590,7 @@ struct PassPlan {
 };
 
 struct Workspace {
-  DevBuf arena, small, partial, result, ovf, grad, bucket;
+  DevBuf arena, small, partial, result, ovf, grad, bucket, nbrcol;
 };
 
 Workspace &workspace() {
@@ -734,6 +734,8 @@ struct Ctx {
   size_t lds_max = 65536;
   int bucket_j0 = -1;  // pass whose colour buckets are in ws->bucket
   int bucket_b = 0;
+  int nbr_j0 = -1;     // pass whose neighbour colours are in ws->nbrcol
+  int nbr_b = 0;
 };
 
 sg2v_status bind_tables(Ctx &x) {
@@ -877,8 +879,17 @@ sg2v_status step_spmm(Ctx &x, int node) {
   a.colors = x.c->d;
   a.j0 = x.j0;
   a.n = x.g->n;
-  if (!(tuning().flags & SG2V_TUNE_NO_COLOR_SKIP))
+  a.nbr_col = nullptr;
+  a.nnz = x.g->nnz;
+  if (!(tuning().flags & SG2V_TUNE_NO_COLOR_SKIP)) {
     ST_TRY(chunk_masks(x, node, W, &a.chunk_jb, &a.chunk_union, &a.chunk_inter));
+    if (x.nbr_j0 != x.j0 || x.nbr_b != x.b) {
+      launch_nbr_colors(x.g->col_idx, x.g->nnz, x.c->d, x.g->n, x.j0, x.b, (uint8_t *)x.ws->nbrcol.p, x.s);
+      x.nbr_j0 = x.j0;
+      x.nbr_b = x.b;
+    }
+    a.nbr_col = (const uint8_t *)x.ws->nbrcol.p;
+  }
   if (x.dt == DT_F32) launch_fill_u32(B.mx, nc, 0u, x.s);
   const int64_t chunks = (nc + W - 1) / W;
   dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
@@ -888,7 +899,8 @@ sg2v_status step_spmm(Ctx &x, int node) {
     const double bytes = 2.0 * n * (double)nc * x.es +
                          (double)chunks * (nnz * (4.0 + (x.g->w ? 4.0 : 0.0)) + 20.0 * x.g->n_tasks);
     ProfScope ps(SG2V_K_SPMM, bytes, nnz * (double)nc, x.s);
-    if (launch_spmm(x.dt, a, x.pp.G, grid, x.s)) {
+    const int unroll = (tuning().flags & SG2V_TUNE_SPMM_UNROLL8) ? 8 : 4;
+    if (launch_spmm(x.dt, a, x.pp.G, unroll, grid, x.s)) {
       set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
       return SG2V_EINVAL;
     }
@@ -1280,8 +1292,11 @@ sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_col
   ST_TRY(x.ws->partial.ensure((size_t)1024 * b * 8));
   ST_TRY(x.ws->ovf.ensure(256));
   ST_TRY(x.ws->bucket.ensure((size_t)b * (64 + g->n) * 4 + 256));
+  if (!(tuning().flags & SG2V_TUNE_NO_COLOR_SKIP))
+    ST_TRY(x.ws->nbrcol.ensure((size_t)b * std::max<int64_t>(g->nnz, 1) + 256));
   x.ovf = (int *)x.ws->ovf.p;
   x.bucket_j0 = -1;
+  x.nbr_j0 = -1;
   return bind_tables(x);
 }
 
@@ -1438,7 +1453,7 @@ struct BatchGraph {
   uint64_t seed = 0;
   int ncol = 0, mode = 0;
   sg2v_tuning_t tune{};
-  uint64_t gens[7] = {0, 0, 0, 0, 0, 0, 0};
+  uint64_t gens[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<std::unique_ptr<sg2v_colorings>> cols;
   hipGraphExec_t exec = nullptr;
   int device = -1;
@@ -1463,6 +1478,7 @@ void ws_gens(Workspace &ws, uint64_t *out) {
   out[4] = ws.ovf.gen;
   out[5] = ws.grad.gen;
   out[6] = ws.bucket.gen;
+  out[7] = ws.nbrcol.gen;
 }
 
 }  // namespace
@@ -1529,13 +1545,13 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
   HIP_TRY(hipStreamSynchronize(us));
 
   // reuse a cached executable graph if every input and buffer is unchanged
-  uint64_t gens[7];
+  uint64_t gens[8];
   ws_gens(ws, gens);
   BatchGraph *hit = nullptr;
   for (auto &e : g_batch_cache) {
     if (e->g == g && e->seed == seed && e->ncol == ncol && e->mode == mode && e->device == dev &&
         e->plans == bg->plans && same_tuning(e->tune, bg->tune) &&
-        std::equal(gens, gens + 7, e->gens))
+        std::equal(gens, gens + 8, e->gens))
       hit = e.get();
   }
   char *res = (char *)ws.result.p;
@@ -1779,13 +1795,15 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
         a.colors = c->d;
         a.j0 = j;
         a.n = g->n;
+        a.nbr_col = nullptr;
+        a.nnz = g->nnz;
         const int64_t chunks = (cp + W - 1) / W;
         dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
                   (unsigned)chunks);
         {
           ProfScope ps(SG2V_K_SPMM, 2.0 * g->n * cp * 8 + (double)chunks * g->nnz * 8,
                        (double)g->nnz * cp, s);
-          if (launch_spmm(DT_F64, a, x.pp.G, grid, s)) {
+          if (launch_spmm(DT_F64, a, x.pp.G, 4, grid, s)) {
             set_error("sg2v_count_grad: no SpMM variant for G=%d", x.pp.G);
             return SG2V_EINVAL;
           }
@@ -1972,11 +1990,12 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
   std::vector<sg2v_tuning_t> cand;
   const int widths[] = {16, 32, 64};
   const int rows[] = {4, 8, 16};
+  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL8;
   for (int w : widths)
-    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP}) {
+    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL8}) {
       sg2v_tuning_t t = base;
       t.spmm_width = w;
-      t.flags = (base.flags & ~SG2V_TUNE_NO_COLOR_SKIP) | fl;
+      t.flags = (base.flags & ~skipfl) | fl;
       cand.push_back(t);
     }
   sg2v_tuning_t best = base;

@@ -207,8 +207,8 @@ def test_spmm_widths_agree(small_rmat):
     old = sg.get_tuning()
     try:
         for w in (8, 16, 32, 64):
-            for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA,
-                       sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA):
+            for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA, sg.TUNE_SPMM_UNROLL8,
+                       sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA | sg.TUNE_SPMM_UNROLL8):
                 sg.set_tuning(spmm_width=w, flags=fl)
                 say("spmm width", w, "flags", fl)
                 got = sg.count(p, g, c, "u64")["colorful_u64"]
