@@ -239,7 +239,9 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
  * (vertices grouped by colour); budget_bytes: device memory the count may use. */
 #define SG2V_TUNE_NO_COLOR_SKIP 1
 #define SG2V_TUNE_NO_COLOR_EMA 2
-#define SG2V_TUNE_SPMM_UNROLL8 4 /* 8 row gathers in flight per SpMM stream instead of 4 */
+#define SG2V_TUNE_SPMM_UNROLL4 4 /* 4 row gathers in flight per SpMM stream instead of 8 */
+#define SG2V_TUNE_NO_XSPLIT 8    /* no neighbour-range split of long SpMM tasks over the XCDs */
+#define SG2V_TUNE_FORCE_XSPLIT 16 /* split even when a chunk fits the caches (tests) */
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;

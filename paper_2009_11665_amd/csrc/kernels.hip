@@ -107,12 +107,19 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   const int sub = lane % G;
-  const int64_t col0 = (int64_t)blockIdx.y * W + sub * N;
+  const int64_t chunk = a.chunk0 + blockIdx.y;
+  const int64_t col0 = chunk * W + sub * N;
+  // Neighbour-range split of the first xunits units (the long tasks): block b
+  // gathers only neighbours in range b % xsplit (workgroups go to the XCDs
+  // round-robin, so each XCD's L2 serves one range) and writes a partial row
+  // per task, summed in range order by k_xsplit_combine.  The other units are
+  // processed whole by every block.
+  const int xr = a.xsplit ? (int)(blockIdx.x % a.xsplit) : 0;
   // colour skipping for this chunk
-  const int jb = a.chunk_jb ? a.chunk_jb[blockIdx.y] : -1;
+  const int jb = a.chunk_jb ? a.chunk_jb[chunk] : -1;
   const uint8_t *colj = jb >= 0 ? a.colors + (int64_t)(a.j0 + jb) * a.n : nullptr;
-  const uint32_t umask = jb >= 0 ? a.chunk_union[blockIdx.y] : 0xFFFFFFFFu;
-  const uint32_t imask = jb >= 0 ? a.chunk_inter[blockIdx.y] : 0u;
+  const uint32_t umask = jb >= 0 ? a.chunk_union[chunk] : 0xFFFFFFFFu;
+  const uint32_t imask = jb >= 0 ? a.chunk_inter[chunk] : 0u;
   const T *__restrict__ M = (const T *)a.M;
   T *__restrict__ B = (T *)a.B;
   T *__restrict__ Pt = (T *)a.partial;
@@ -121,7 +128,12 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
 #pragma unroll
   for (int u = 0; u < N; ++u) cmax[u] = T(0);
 
-  for (int64_t unit = blockIdx.x; unit < a.n_units; unit += gridDim.x) {
+  for (int phase = a.xsplit ? 0 : 1; phase < 2; ++phase) {
+  const bool split = phase == 0;
+  const int64_t ustart = split ? blockIdx.x / a.xsplit : a.xunits + blockIdx.x;
+  const int64_t ustep = split ? gridDim.x / a.xsplit : gridDim.x;
+  const int64_t uend = split ? a.xunits : a.n_units;
+  for (int64_t unit = ustart; unit < uend; unit += ustep) {
     const int rpw = a.unit_rpw[unit];
     const int lpt = WAVE / rpw;        // lanes per task
     const int tloc = lane / lpt;       // task within the wave
@@ -131,14 +143,19 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
     const int gbase = tloc * lpt;      // first lane of the task's group
     const int tidx = wv * rpw + tloc;
     const bool valid = tidx < a.unit_ntask[unit];
-    int64_t beg = 0;
+    int64_t beg = 0, t = 0;
     int len = 0, row = 0, slot = -1;
     if (valid) {
-      const int64_t t = (int64_t)a.unit_task[unit] + tidx;
+      t = (int64_t)a.unit_task[unit] + tidx;
       row = a.task_row[t];
       beg = a.task_beg[t];
       len = a.task_len[t];
       slot = a.task_slot[t];
+      if (split) {
+        const uint16_t *sp = a.tsplit + t * (a.xsplit + 1);
+        beg += sp[xr];
+        len = sp[xr + 1] - sp[xr];
+      }
       if (colj && (imask >> colj[row] & 1u)) len = 0;  // row never read here: zeros
     }
     const uint64_t gmask = (lpt == 64) ? ~0ull : (((1ull << lpt) - 1ull) << gbase);
@@ -237,7 +254,9 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       for (int off = G; off < lpt; off <<= 1) x = A::add(x, shfl_xor(x, off), ovf);
       acc0.x[u] = x;
     }
-    if (valid && stream == 0) {
+    if (valid && stream == 0 && split) {
+      *(V16<T> *)((T *)a.partial8 + ((int64_t)xr * a.n_tasks + t) * a.ldp + (int64_t)blockIdx.y * W + sub * N) = acc0;
+    } else if (valid && stream == 0) {
       if (slot < 0) {
         if (a.accumulate) {
           const V16<T> old = *(const V16<T> *)(B + (int64_t)row * a.ldb + col0);
@@ -253,6 +272,7 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       }
     }
   }
+  }  // phase
   if constexpr (is_u64<T>) {
     // U64: flags only for valid columns are meaningful; padding columns may
     // hold arbitrary bits and are excluded by the caller zeroing padding.
@@ -278,6 +298,79 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       }
       __syncthreads();
     }
+  }
+}
+
+// Sum the xsplit partial rows of every task in range order: rows held in one
+// task go to B (and the column maximum), segments of long rows to their slot
+// of the long-row partial buffer.  Grid: (column vectors of the chunk group,
+// groups of tasks).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_xsplit_combine(XsplitCombineArgs a) {
+  constexpr int N = V16<T>::N;
+  using A = Arith<T>;
+  const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // vector within the group
+  const int64_t cl = v * N;                                       // column within the group
+  if (cl >= a.ldp) return;
+  const int64_t cg = a.col_first + cl;  // column of B
+  const T *P = (const T *)a.partial8;
+  T *B = (T *)a.B;
+  T *H = (T *)a.hub;
+  bool ovf = false;
+  T cmax[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) cmax[u] = T(0);
+  for (int64_t t = blockIdx.y; t < a.n_tasks; t += gridDim.y) {
+    V16<T> acc = *(const V16<T> *)(P + t * a.ldp + cl);
+    for (int x = 1; x < a.xsplit; ++x) {
+      const V16<T> w = *(const V16<T> *)(P + ((int64_t)x * a.n_tasks + t) * a.ldp + cl);
+#pragma unroll
+      for (int u = 0; u < N; ++u) acc.x[u] = A::add(acc.x[u], w.x[u], ovf);
+    }
+    const int slot = a.task_slot[t];
+    if (slot < 0) {
+      T *dst = B + (int64_t)a.task_row[t] * a.ldb + cg;
+      if (a.accumulate) {
+        const V16<T> old = *(const V16<T> *)dst;
+#pragma unroll
+        for (int u = 0; u < N; ++u) acc.x[u] = A::add(acc.x[u], old.x[u], ovf);
+      }
+      *(V16<T> *)dst = acc;
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (cg + u < a.ncols_valid && acc.x[u] > cmax[u]) cmax[u] = acc.x[u];
+    } else {
+      *(V16<T> *)(H + (int64_t)slot * a.ldb + cg) = acc;
+    }
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf && cg < a.ncols_valid) atomicOr(a.ovf, 1);
+  }
+  if (a.mx) {
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (cg + u < a.ncols_valid && (float)cmax[u] > 0.f)
+        atomicMax(a.mx + cg + u, __float_as_uint((float)cmax[u]));
+  }
+}
+
+// Split points of every task's neighbour list at the range boundaries
+// r * ceil(n / xs), r = 0..xs (neighbour lists are sorted).
+__global__ void k_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
+                             int64_t n_tasks, int64_t n, int xs, uint16_t *out) {
+  const int64_t span = (n + xs - 1) / xs;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_tasks * (xs + 1);
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = q / (xs + 1);
+    const int r = (int)(q - t * (xs + 1));
+    const int32_t *c = col_idx + task_beg[t];
+    int lo = 0, hi = task_len[t];
+    const int64_t bound = (int64_t)r * span;
+    while (lo < hi) {  // first entry with column >= bound
+      const int mid = (lo + hi) >> 1;
+      if (c[mid] < bound) lo = mid + 1; else hi = mid;
+    }
+    out[q] = (uint16_t)lo;
   }
 }
 
@@ -937,6 +1030,23 @@ int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipS
   if (dtype == DT_F32) return spmm_t<float, 4>(a, G, grid, s);
   if (dtype == DT_F64) return spmm_t<double, 4>(a, G, grid, s);
   return spmm_t<uint64_t, 4>(a, G, grid, s);
+}
+
+void launch_xsplit_combine(int dtype, const XsplitCombineArgs &a, hipStream_t s) {
+  const int N = (dtype == DT_F32) ? 4 : 2;
+  const int64_t nvec = (a.ldp + N - 1) / N;
+  dim3 grid(grid_cap((nvec + BLOCK - 1) / BLOCK, 1 << 20), grid_cap((a.n_tasks + 63) / 64, 8192));
+  if (dtype == DT_F32) k_xsplit_combine<float><<<grid, BLOCK, 0, s>>>(a);
+  else if (dtype == DT_F64) k_xsplit_combine<double><<<grid, BLOCK, 0, s>>>(a);
+  else k_xsplit_combine<uint64_t><<<grid, BLOCK, 0, s>>>(a);
+}
+
+void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
+                       int64_t n_tasks, int64_t n, int xs, uint16_t *out, hipStream_t s) {
+  const int64_t total = n_tasks * (xs + 1);
+  if (total == 0) return;
+  k_task_split<<<grid_cap((total + BLOCK - 1) / BLOCK, 65536), BLOCK, 0, s>>>(col_idx, task_beg, task_len,
+                                                                            n_tasks, n, xs, out);
 }
 
 void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s) {

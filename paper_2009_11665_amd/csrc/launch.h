@@ -54,6 +54,30 @@ struct SpmmArgs {
   int64_t n;
   const uint8_t *nbr_col;  // [b][nnz] colour of col_idx[e] in each colouring of the pass
   int64_t nnz;
+  int64_t chunk0;          // first chunk of this launch (blockIdx.y is relative)
+  // neighbour-range split (0: off) of units [0, xunits), whose tasks are
+  // [0, n_tasks): partial rows to partial [xsplit][n_tasks][ldp]
+  int32_t xsplit;
+  int64_t xunits;
+  const uint16_t *tsplit;  // [tasks][xsplit + 1] split offsets within each task
+  int64_t n_tasks;
+  int64_t ldp;
+  void *partial8;
+};
+
+struct XsplitCombineArgs {
+  const void *partial8;  // [xsplit][n_tasks][ldp]
+  int32_t xsplit;
+  int64_t n_tasks, ldp;
+  int64_t col_first;     // column of B where this chunk group starts
+  const int32_t *task_row, *task_slot;
+  void *B;
+  int64_t ldb;
+  void *hub;             // long-row partial rows [n_slots][ldb]
+  int64_t ncols_valid;
+  unsigned *mx;
+  int *ovf;
+  int32_t accumulate;
 };
 
 struct CombineArgs {
@@ -163,6 +187,9 @@ void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s);
 // unroll: gathers in flight per stream (4 or 8)
 int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipStream_t s);
 void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s);
+void launch_xsplit_combine(int dtype, const XsplitCombineArgs &a, hipStream_t s);
+void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
+                       int64_t n_tasks, int64_t n, int xs, uint16_t *out, hipStream_t s);
 int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
                        hipStream_t s);
 void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s);

@@ -55,6 +55,8 @@ sg2v_tuning_t tuning() {
 
 constexpr int64_t kSegment = 4096;  // neighbours per SpMM task (longer rows are split)
 constexpr int kPersistBlocks = 2048;
+constexpr int kXsplit = 8;          // neighbour ranges (one per XCD)
+constexpr int64_t kXsplitMin = 128; // tasks at least this long are split by range
 
 int dtype_of(sg2v_mode m) { return m == SG2V_FP32S ? DT_F32 : (m == SG2V_FP64 ? DT_F64 : DT_U64); }
 int esize_of(int dt) { return dt == DT_F32 ? 4 : 8; }
@@ -164,6 +166,8 @@ struct UnitTable {
   int8_t *unit_rpw = nullptr;
   int16_t *unit_ntask = nullptr;
   int64_t n_units = 0;
+  int64_t x_units = 0;  // leading units whose tasks are split by neighbour range
+  int64_t x_tasks = 0;  // tasks in those units
 };
 
 struct sg2v_graph {
@@ -182,8 +186,10 @@ struct sg2v_graph {
   int32_t *long_row = nullptr, *long_slot0 = nullptr, *long_nslot = nullptr;
   int32_t n_long = 0;
   std::map<int, UnitTable> units;  // by G (lanes per neighbour row segment)
+  uint16_t *tsplit = nullptr;      // [n_tasks][kXsplit + 1] neighbour-range split offsets
   std::vector<void *> allocs;
   ~sg2v_graph() {
+    if (tsplit) (void)hipFree(tsplit);
     for (void *p : allocs) (void)hipFree(p);
     for (auto &kv : units) {
       (void)hipFree(kv.second.unit_task);
@@ -238,6 +244,8 @@ sg2v_status build_units(sg2v_graph *g, int G, hipStream_t s, UnitTable **out) {
   }
   UnitTable U;
   U.n_units = (int64_t)ut.size();
+  while (U.x_units < U.n_units && g->h_task_len[ut[U.x_units]] >= kXsplitMin) ++U.x_units;
+  U.x_tasks = U.x_units < U.n_units ? ut[U.x_units] : g->n_tasks;
   ST_TRY(upload(ut, (void **)&U.unit_task, s));
   ST_TRY(upload(ur, (void **)&U.unit_rpw, s));
   ST_TRY(upload(un, (void **)&U.unit_ntask, s));
@@ -590,7 +598,7 @@ struct PassPlan {
 };
 
 struct Workspace {
-  DevBuf arena, small, partial, result, ovf, grad, bucket, nbrcol;
+  DevBuf arena, small, partial, result, ovf, grad, bucket, nbrcol, xpart;
 };
 
 Workspace &workspace() {
@@ -846,6 +854,29 @@ sg2v_status chunk_masks(Ctx &x, int node, int W, const int32_t **jb, const uint3
   return SG2V_OK;
 }
 
+// Neighbour-range split of the SpMM's long tasks: used when one column chunk
+// of the gathered table is much larger than an XCD's L2.  Returns the chunk
+// group size (0: no split) after making sure the split offsets and the
+// partial-row buffer exist.
+sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t *group) {
+  *group = 0;
+  if ((tuning().flags & SG2V_TUNE_NO_XSPLIT) || U->x_units == 0) return SG2V_OK;
+  if (!(tuning().flags & SG2V_TUNE_FORCE_XSPLIT) && (double)x.g->n * W * x.es < 32.0 * (1 << 20))
+    return SG2V_OK;
+  sg2v_graph *g = x.g;
+  if (!g->tsplit) {
+    HIP_TRY(hipMalloc((void **)&g->tsplit, (size_t)g->n_tasks * (kXsplit + 1) * sizeof(uint16_t)));
+    launch_task_split(g->col_idx, g->task_beg, g->task_len, g->n_tasks, g->n, kXsplit, g->tsplit, x.s);
+    HIP_TRY(hipGetLastError());
+  }
+  const int64_t chunks = (nc + W - 1) / W;
+  const double per_chunk = (double)kXsplit * U->x_tasks * W * x.es;
+  const int64_t gch = std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)((4.0 * (1 << 30)) / per_chunk)));
+  ST_TRY(x.ws->xpart.ensure((size_t)(per_chunk * gch) + 256));
+  *group = gch;
+  return SG2V_OK;
+}
+
 sg2v_status step_spmm(Ctx &x, int node) {
   Tab &Mp = x.pp.M[node];
   Tab &B = x.pp.B[node];
@@ -892,18 +923,70 @@ sg2v_status step_spmm(Ctx &x, int node) {
   }
   if (x.dt == DT_F32) launch_fill_u32(B.mx, nc, 0u, x.s);
   const int64_t chunks = (nc + W - 1) / W;
-  dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
-            (unsigned)chunks);
-  {
-    const double n = (double)x.g->n, nnz = (double)x.g->nnz;
-    const double bytes = 2.0 * n * (double)nc * x.es +
-                         (double)chunks * (nnz * (4.0 + (x.g->w ? 4.0 : 0.0)) + 20.0 * x.g->n_tasks);
+  const int unroll = (tuning().flags & SG2V_TUNE_SPMM_UNROLL4) ? 4 : 8;
+  a.chunk0 = 0;
+  a.xsplit = 0;
+  a.xunits = 0;
+  a.tsplit = nullptr;
+  a.n_tasks = 0;
+  a.ldp = 0;
+  a.partial8 = nullptr;
+  int64_t gch = 0;
+  ST_TRY(xsplit_setup(x, U, nc, W, &gch));
+  const double n = (double)x.g->n, nnz = (double)x.g->nnz;
+  const double bytes = 2.0 * n * (double)nc * x.es +
+                       (double)chunks * (nnz * (4.0 + (x.g->w ? 4.0 : 0.0)) + 20.0 * x.g->n_tasks);
+  if (gch == 0) {
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
+              (unsigned)chunks);
     ProfScope ps(SG2V_K_SPMM, bytes, nnz * (double)nc, x.s);
-    const int unroll = (tuning().flags & SG2V_TUNE_SPMM_UNROLL8) ? 8 : 4;
     if (launch_spmm(x.dt, a, x.pp.G, unroll, grid, x.s)) {
       set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
       return SG2V_EINVAL;
     }
+  } else {
+    // long tasks split over the XCDs' neighbour ranges, chunk group by group
+    unsigned *mx = a.mx;
+    a.mx = nullptr;  // column maxima of split tasks come from the combine
+    a.xsplit = kXsplit;
+    a.xunits = U->x_units;
+    a.tsplit = x.g->tsplit;
+    a.n_tasks = U->x_tasks;
+    a.partial8 = x.ws->xpart.p;
+    const int64_t gx = std::max<int64_t>(kXsplit, std::min<int64_t>(U->n_units * kXsplit, kPersistBlocks) / kXsplit * kXsplit);
+    for (int64_t c0 = 0; c0 < chunks; c0 += gch) {
+      const int64_t gc = std::min(gch, chunks - c0);
+      const double frac = (double)gc / (double)chunks;
+      a.chunk0 = c0;
+      a.ldp = gc * W;
+      a.mx = mx;  // whole (unsplit) tasks still fold their maxima in the kernel
+      {
+        ProfScope ps(SG2V_K_SPMM, bytes * frac, nnz * (double)nc * frac, x.s);
+        if (launch_spmm(x.dt, a, x.pp.G, unroll, dim3((unsigned)gx, (unsigned)gc), x.s)) {
+          set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
+          return SG2V_EINVAL;
+        }
+      }
+      XsplitCombineArgs xc;
+      xc.partial8 = a.partial8;
+      xc.xsplit = kXsplit;
+      xc.n_tasks = a.n_tasks;
+      xc.ldp = a.ldp;
+      xc.col_first = c0 * W;
+      xc.task_row = x.g->task_row;
+      xc.task_slot = x.g->task_slot;
+      xc.B = B.p;
+      xc.ldb = B.ld;
+      xc.hub = a.partial;
+      xc.ncols_valid = nc;
+      xc.mx = mx;
+      xc.ovf = x.ovf;
+      xc.accumulate = 0;
+      ProfScope pc(SG2V_K_SPMM_COMBINE, 2.0 * kXsplit * (double)a.n_tasks * a.ldp * x.es,
+                   (double)a.n_tasks * a.ldp, x.s);
+      launch_xsplit_combine(x.dt, xc, x.s);
+    }
+    a.mx = mx;
   }
   CombineArgs cb;
   cb.partial = a.partial;
@@ -1453,7 +1536,7 @@ struct BatchGraph {
   uint64_t seed = 0;
   int ncol = 0, mode = 0;
   sg2v_tuning_t tune{};
-  uint64_t gens[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t gens[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<std::unique_ptr<sg2v_colorings>> cols;
   hipGraphExec_t exec = nullptr;
   int device = -1;
@@ -1479,6 +1562,7 @@ void ws_gens(Workspace &ws, uint64_t *out) {
   out[5] = ws.grad.gen;
   out[6] = ws.bucket.gen;
   out[7] = ws.nbrcol.gen;
+  out[8] = ws.xpart.gen;
 }
 
 }  // namespace
@@ -1545,13 +1629,13 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
   HIP_TRY(hipStreamSynchronize(us));
 
   // reuse a cached executable graph if every input and buffer is unchanged
-  uint64_t gens[8];
+  uint64_t gens[9];
   ws_gens(ws, gens);
   BatchGraph *hit = nullptr;
   for (auto &e : g_batch_cache) {
     if (e->g == g && e->seed == seed && e->ncol == ncol && e->mode == mode && e->device == dev &&
         e->plans == bg->plans && same_tuning(e->tune, bg->tune) &&
-        std::equal(gens, gens + 8, e->gens))
+        std::equal(gens, gens + 9, e->gens))
       hit = e.get();
   }
   char *res = (char *)ws.result.p;
@@ -1990,9 +2074,9 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
   std::vector<sg2v_tuning_t> cand;
   const int widths[] = {16, 32, 64};
   const int rows[] = {4, 8, 16};
-  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL8;
+  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_NO_XSPLIT;
   for (int w : widths)
-    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL8}) {
+    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL4, (int)SG2V_TUNE_NO_XSPLIT}) {
       sg2v_tuning_t t = base;
       t.spmm_width = w;
       t.flags = (base.flags & ~skipfl) | fl;

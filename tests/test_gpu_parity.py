@@ -201,14 +201,16 @@ def test_batching_invariance(small_rmat):
 def test_spmm_widths_agree(small_rmat):
     par, k = gg.CATERPILLAR10, 10
     g = sg.Graph.from_csr(small_rmat)
+    assert small_rmat.degrees().max() >= 128  # some tasks take the neighbour-range split
     c = sg.Colorings(g, k, 2, 2)
     p = sg.Plan(par, k)
     ref = [x[1] for x in oracle_counts(small_rmat, par, k, 2, 2, O.U64)]
     old = sg.get_tuning()
     try:
         for w in (8, 16, 32, 64):
-            for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA, sg.TUNE_SPMM_UNROLL8,
-                       sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA | sg.TUNE_SPMM_UNROLL8):
+            for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA, sg.TUNE_SPMM_UNROLL4,
+                       sg.TUNE_FORCE_XSPLIT, sg.TUNE_FORCE_XSPLIT | sg.TUNE_NO_COLOR_SKIP,
+                       sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA | sg.TUNE_SPMM_UNROLL4):
                 sg.set_tuning(spmm_width=w, flags=fl)
                 say("spmm width", w, "flags", fl)
                 got = sg.count(p, g, c, "u64")["colorful_u64"]
@@ -238,8 +240,10 @@ def test_edge_cases():
         assert [int(x) for x in r["colorful_u64"]] == [x[1] for x in ref]
 
 
-def test_long_rows_split_across_tasks():
-    """Rows longer than one SpMM task are split and their partial rows summed."""
+@pytest.mark.parametrize("flags", [0, 16])
+def test_long_rows_split_across_tasks(flags):
+    """Rows longer than one SpMM task are split and their partial rows summed
+    (flags 16: also split every long task over the neighbour ranges)."""
     rng = np.random.default_rng(9)
     n = 12_000
     edges = {(0, v) for v in range(1, 9001)} | {(1, v) for v in range(2, 5002)}
@@ -248,16 +252,21 @@ def test_long_rows_split_across_tasks():
         if a != b:
             edges.add((min(a, b), max(a, b)))
     G = gg.from_edge_list(n, sorted(edges))
-    for par in (gg.PATH5, gg.BINTREE7):
-        k = len(par)
-        say("long rows", par)
-        ref = oracle_counts(G, par, k, 6, 2, O.U64)
-        ref64 = oracle_counts(G, par, k, 6, 2, O.FP64)
-        r = gpu_counts(G, par, k, 6, 2, "u64")
-        r32 = gpu_counts(G, par, k, 6, 2, "fp32s")
-        for j in range(2):
-            assert int(r["colorful_u64"][j]) == ref[j][1]
-            assert r32["colorful"][j] == pytest.approx(ref64[j][0], rel=FP32_TOL)
+    old = sg.get_tuning()
+    sg.set_tuning(flags=flags)
+    try:
+        for par in (gg.PATH5, gg.BINTREE7):
+            k = len(par)
+            say("long rows", par, flags)
+            ref = oracle_counts(G, par, k, 6, 2, O.U64)
+            ref64 = oracle_counts(G, par, k, 6, 2, O.FP64)
+            r = gpu_counts(G, par, k, 6, 2, "u64")
+            r32 = gpu_counts(G, par, k, 6, 2, "fp32s")
+            for j in range(2):
+                assert int(r["colorful_u64"][j]) == ref[j][1]
+                assert r32["colorful"][j] == pytest.approx(ref64[j][0], rel=FP32_TOL)
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
 
 
 def test_u64_overflow_flag():
