@@ -240,8 +240,10 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
 #define SG2V_TUNE_NO_COLOR_SKIP 1
 #define SG2V_TUNE_NO_COLOR_EMA 2
 #define SG2V_TUNE_SPMM_UNROLL4 4 /* 4 row gathers in flight per SpMM stream instead of 8 */
-#define SG2V_TUNE_NO_XSPLIT 8    /* no neighbour-range split of long SpMM tasks over the XCDs */
+#define SG2V_TUNE_NO_XSPLIT 8    /* never split long SpMM tasks over the XCDs (overrides the two below) */
 #define SG2V_TUNE_FORCE_XSPLIT 16 /* split even when a chunk fits the caches (tests) */
+#define SG2V_TUNE_XSPLIT 32      /* split long SpMM tasks over the XCDs' neighbour ranges when one
+                                    column chunk of the gathered table exceeds 32 MB (off by default) */
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;

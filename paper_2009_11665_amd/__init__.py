@@ -321,6 +321,7 @@ TUNE_NO_COLOR_EMA = 2
 TUNE_SPMM_UNROLL4 = 4
 TUNE_NO_XSPLIT = 8
 TUNE_FORCE_XSPLIT = 16
+TUNE_XSPLIT = 32
 
 
 def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,

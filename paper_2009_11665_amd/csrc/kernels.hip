@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       if (wv == 0 && lane < G) {
         float x = red[0][lane];
         for (int q = 1; q < WAVES_PER_BLOCK; ++q) x = fmaxf(x, red[q][lane]);
-        const int64_t c = (int64_t)blockIdx.y * W + lane * N + u;
+        const int64_t c = chunk * W + lane * N + u;
         if (c < a.ncols_valid && x > 0.f) atomicMax(a.mx + c, __float_as_uint(x));
       }
       __syncthreads();

@@ -860,8 +860,10 @@ sg2v_status chunk_masks(Ctx &x, int node, int W, const int32_t **jb, const uint3
 // partial-row buffer exist.
 sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t *group) {
   *group = 0;
-  if ((tuning().flags & SG2V_TUNE_NO_XSPLIT) || U->x_units == 0) return SG2V_OK;
-  if (!(tuning().flags & SG2V_TUNE_FORCE_XSPLIT) && (double)x.g->n * W * x.es < 32.0 * (1 << 20))
+  const int fl = tuning().flags;
+  if ((fl & SG2V_TUNE_NO_XSPLIT) || U->x_units == 0) return SG2V_OK;
+  if (!(fl & SG2V_TUNE_FORCE_XSPLIT) &&
+      (!(fl & SG2V_TUNE_XSPLIT) || (double)x.g->n * W * x.es < 32.0 * (1 << 20)))
     return SG2V_OK;
   sg2v_graph *g = x.g;
   if (!g->tsplit) {
@@ -2074,9 +2076,9 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
   std::vector<sg2v_tuning_t> cand;
   const int widths[] = {16, 32, 64};
   const int rows[] = {4, 8, 16};
-  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_NO_XSPLIT;
+  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_XSPLIT;
   for (int w : widths)
-    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL4, (int)SG2V_TUNE_NO_XSPLIT}) {
+    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL4, (int)SG2V_TUNE_XSPLIT}) {
       sg2v_tuning_t t = base;
       t.spmm_width = w;
       t.flags = (base.flags & ~skipfl) | fl;
