@@ -85,6 +85,53 @@ def load_traffic():
     return d.get("hbm_bytes_per_launch")
 
 
+def pmc_per_dispatch(db, counter):
+    """(kernel name, value) per dispatch of one counter from a rocprofv3 rocpd
+    database (table counters_collection)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    try:
+        rows = con.execute("select dispatch_id, kernel_name, value from counters_collection "
+                           "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
+    finally:
+        con.close()
+    return [(r[1], float(r[2])) for r in rows]
+
+
+def write_traffic(spmm_fetch, spmm_write, copy_fetch, copy_write, copy_mib):
+    """HBM bytes per SpMM launch from rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch), each scaled by what the same counter
+    reads for a device copy of copy_mib MiB."""
+    def mean_of(db, counter, pick):
+        v = [x for name, x in pmc_per_dispatch(db, counter) if pick(name)]
+        if not v:
+            raise SystemExit(f"no matching dispatches of {counter} in {db}")
+        return sum(v) / len(v), len(v)
+
+    is_spmm = lambda name: "k_spmm<float" in name  # noqa: E731
+    is_copy = lambda name: "copyBuffer" in name  # noqa: E731
+    nbytes = copy_mib * (1 << 20)
+    cf, _ = mean_of(copy_fetch, "FETCH_SIZE", is_copy)
+    cw, _ = mean_of(copy_write, "WRITE_SIZE", is_copy)
+    f_fetch, f_write = nbytes / (cf * 1024.0), nbytes / (cw * 1024.0)
+    sf, nf = mean_of(spmm_fetch, "FETCH_SIZE", is_spmm)
+    sw, nw = mean_of(spmm_write, "WRITE_SIZE", is_spmm)
+    rd, wr = sf * 1024.0 * f_fetch, sw * 1024.0 * f_write
+    out = {"kernel": "k_spmm<float,...>", "kernel_source_sha": kernel_sha(),
+           "hbm_bytes_per_launch": rd + wr, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+           "launches": [nf, nw], "fetch_size_kib_per_launch": sf, "write_size_kib_per_launch": sw,
+           "calibration": {"copy_bytes": nbytes, "fetch_factor": f_fetch, "write_factor": f_write},
+           "runs": ["rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --steps 1 --warmup 0 "
+                    "--no-cpu-baseline --no-fp64 --colorings 1",
+                    "rocprofv3 --pmc WRITE_SIZE -- (same)",
+                    f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --calibrate-copy {copy_mib}",
+                    f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --calibrate-copy {copy_mib}"]}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
 def cpu_baseline(parent, k, scale, seed, full_n, full_nnz):
     """The oracle (FP64, OpenMP over vertices) on a bounded sample: the same
     template and colouring rule on an RMAT graph of 2^scale vertices with the
@@ -128,7 +175,14 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("SPMM_FETCH", "SPMM_WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the SpMM traffic file from four rocprofv3 --pmc databases "
+                         "(--calibrate-copy gives the copy size, default 1024 MiB) and exit")
     args = ap.parse_args()
+
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, args.calibrate_copy or 1024)
+        return
 
     if args.calibrate_copy:
         import torch
@@ -253,6 +307,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
             "traffic_over_algorithmic": (traffic / (sp["bytes"] / sp["launches"])) if traffic else None,
+            "launches_per_step": sp["launches"] / args.steps,
+            "avg_launch_ms": sp["ms"] / sp["launches"] if sp["launches"] else None,
             "gather_model_GBps": (sp["work"] * 4 / (sp["ms"] * 1e-3) / 1e9) if sp["ms"] else None,
         },
         "cpu_baseline": None,

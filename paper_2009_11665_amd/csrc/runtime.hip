@@ -776,7 +776,7 @@ void norm(Ctx &x, Tab &t) {
 
 sg2v_status step_hist(Ctx &x, int node) {
   Tab &H = x.pp.B[node];
-  HistArgs a;
+  HistArgs a{};
   a.row_ptr = x.g->row_ptr;
   a.col_idx = x.g->col_idx;
   a.w = x.g->w;
@@ -887,7 +887,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
   const int N = x.dt == DT_F32 ? 4 : 2;
   const int W = x.pp.G * N;
   const int64_t nc = Mp.cols * x.b;
-  SpmmArgs a;
+  SpmmArgs a{};
   a.col_idx = x.g->col_idx;
   a.w = x.g->w;
   a.task_row = x.g->task_row;
@@ -969,7 +969,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
           return SG2V_EINVAL;
         }
       }
-      XsplitCombineArgs xc;
+      XsplitCombineArgs xc{};
       xc.partial8 = a.partial8;
       xc.xsplit = kXsplit;
       xc.n_tasks = a.n_tasks;
@@ -990,7 +990,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
     }
     a.mx = mx;
   }
-  CombineArgs cb;
+  CombineArgs cb{};
   cb.partial = a.partial;
   cb.B = B.p;
   cb.ld = B.ld;
@@ -1053,7 +1053,7 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
     x.bucket_j0 = x.j0;
     x.bucket_b = x.b;
   }
-  EmaColourArgs a;
+  EmaColourArgs a{};
   a.Ma = g.Ma;
   a.lda = g.lda;
   a.Ca = g.Ca;
@@ -1116,7 +1116,7 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
   const Node &nd = P.nodes[node];
   Tab &Ms = x.pp.M[node];
   Tab &Bt = x.pp.B[nd.passive];
-  EmaArgs a;
+  EmaArgs a{};
   std::memset(&a, 0, sizeof(a));
   a.B = Bt.p;
   a.ldb = Bt.ld;
@@ -1187,7 +1187,7 @@ namespace {
 sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const Plan &P = *x.P;
   const Node &nd = P.nodes[node];
-  RootArgs a;
+  RootArgs a{};
   std::memset(&a, 0, sizeof(a));
   Tab *X = nullptr, *Y = nullptr;
   if (P.root_kind == ROOT_SINGLE) {
@@ -1775,7 +1775,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
       const int64_t cs = nd.cols, ca = A.size == 1 ? P.k : A.cols, cp = Bp.cols;
       // Mbar_a += eMA^T over the active index
       if (A.size > 1) {
-        EmaArgs a;
+        EmaArgs a{};
         std::memset(&a, 0, sizeof(a));
         a.Ma = mbar(q);
         a.lda = ld[q];
@@ -1797,7 +1797,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
       }
       // Bbar over the passive index
       {
-        EmaArgs a;
+        EmaArgs a{};
         std::memset(&a, 0, sizeof(a));
         a.Ms = bbar;
         a.lds = bbar_ld;
@@ -1833,7 +1833,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
       }
       // edge gradient
       {
-        SddmmArgs d;
+        SddmmArgs d{};
         d.row_ptr = g->row_ptr;
         d.col_idx = g->col_idx;
         d.Bbar = bbar;
@@ -1856,7 +1856,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
         UnitTable *U = nullptr;
         ST_TRY(build_units(gg, x.pp.G, s, &U));
         const int W = x.pp.G * 2;
-        SpmmArgs a;
+        SpmmArgs a{};
         a.col_idx = g->col_idx;
         a.w = g->w;
         a.task_row = g->task_row;
@@ -1883,6 +1883,11 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
         a.n = g->n;
         a.nbr_col = nullptr;
         a.nnz = g->nnz;
+        a.chunk0 = 0;  // one launch over every chunk, no neighbour-range split
+        a.xsplit = 0;
+        a.xunits = 0;
+        a.tsplit = nullptr;
+        a.partial8 = nullptr;
         const int64_t chunks = (cp + W - 1) / W;
         dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
                   (unsigned)chunks);
@@ -1894,7 +1899,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
             return SG2V_EINVAL;
           }
         }
-        CombineArgs cb;
+        CombineArgs cb{};
         cb.partial = a.partial;
         cb.B = a.B;
         cb.ld = a.ldb;
