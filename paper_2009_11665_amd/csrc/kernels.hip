@@ -43,42 +43,61 @@ void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t fir
 // Neighbour-colour histogram: B = A_G M_1 where M_1 is the one-hot table of a
 // single-vertex passive child (Alg. 2 sets M_s(i, colour of i) = 1), so
 //   H(i, jj*k + c) = sum_{e in row i} w_e [colour_jj(col_idx[e]) == c].
-// One wave per row, lanes over neighbours; lane c keeps colour c's sum.
-// Unweighted counts use a ballot per colour, weighted sums a fixed-order
-// butterfly, so the result does not depend on scheduling.
+// One wave per SpMM task (a row, or a segment of at most 4096 neighbours of
+// a long row whose partial row goes to its slot and is summed by
+// k_spmm_combine); lanes over neighbours, four blocks of 64 neighbours in
+// flight; lane c keeps colour c's sum.  Unweighted counts use a ballot per
+// colour, weighted sums a fixed-order butterfly, so the result does not
+// depend on scheduling.
 
 template <typename T, bool WEIGHTED>
 __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
+  constexpr int D = 4;
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
   const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
   T *H = (T *)a.H;
-  for (int64_t i = wave; i < a.n; i += nwaves) {
-    const int64_t beg = a.row_ptr[i], end = a.row_ptr[i + 1];
+  T *Pt = (T *)a.partial;
+  for (int64_t t = wave; t < a.n_tasks; t += nwaves) {
+    const int64_t beg = a.task_beg[t];
+    const int len = a.task_len[t];
+    const int slot = a.task_slot[t];
+    T *dst = slot < 0 ? H + (int64_t)a.task_row[t] * a.ldh : Pt + (int64_t)slot * a.ldh;
     for (int jj = 0; jj < a.b; ++jj) {
       const uint8_t *col = a.colors + (int64_t)(a.j0 + jj) * a.n;
       T acc = T(0);
-      for (int64_t base = beg; base < end; base += WAVE) {
-        int64_t e = base + lane;
-        int c = 255;
-        T wv = T(1);
-        if (e < end) {
-          c = col[a.col_idx[e]];
-          if constexpr (WEIGHTED) wv = (T)a.w[e];
+      for (int base = 0; base < len; base += D * WAVE) {
+        int j[D], c[D];
+        float wv[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          const int e = base + q * WAVE + lane;
+          j[q] = e < len ? a.col_idx[beg + e] : -1;
+          wv[q] = 1.0f;
+          if constexpr (WEIGHTED) wv[q] = e < len ? a.w[beg + e] : 0.0f;
         }
-        for (int cc = 0; cc < a.k; ++cc) {
-          if constexpr (!WEIGHTED) {
-            uint64_t m = __ballot(c == cc);
-            if (lane == cc) acc += (T)__popcll(m);
-          } else {
-            T v = (c == cc) ? wv : T(0);
-            for (int off = 1; off < WAVE; off <<= 1) v += shfl_xor(v, off);
-            if (lane == cc) acc += v;
+#pragma unroll
+        for (int q = 0; q < D; ++q) c[q] = j[q] >= 0 ? (int)col[j[q]] : 255;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          if (base + q * WAVE >= len) break;  // uniform
+          for (int cc = 0; cc < a.k; ++cc) {
+            if constexpr (!WEIGHTED) {
+              const uint64_t m = __ballot(c[q] == cc);
+              if (lane == cc) acc += (T)__popcll(m);
+            } else {
+              T v = (c[q] == cc) ? (T)wv[q] : T(0);
+              for (int off = 1; off < WAVE; off <<= 1) v += shfl_xor(v, off);
+              if (lane == cc) acc += v;
+            }
           }
         }
       }
-      if (lane < a.k) H[i * a.ldh + (int64_t)jj * a.k + lane] = acc;
+      if (lane < a.k) dst[(int64_t)jj * a.k + lane] = acc;
     }
+    // partial rows are summed over the whole padded width: clear the padding
+    if (slot >= 0)
+      for (int64_t cidx = (int64_t)a.b * a.k + lane; cidx < a.ldh; cidx += WAVE) dst[cidx] = T(0);
   }
 }
 
@@ -556,9 +575,13 @@ __global__ void k_bucket_count(const uint8_t *colors, int64_t n, int32_t j0, int
   if (threadIdx.x < k && h[threadIdx.x]) atomicAdd(&counts[j * k + threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_bucket_scatter(const uint8_t *colors, int64_t n, int32_t j0, int32_t k,
-                                 const int32_t *counts, int32_t *cursor, int32_t *perm) {
-  __shared__ int off[32];
+// Tiles of BLOCK * 8 rows: positions within the tile from LDS counters, one
+// global reservation per colour and tile.
+__global__ void __launch_bounds__(BLOCK) k_bucket_scatter(const uint8_t *colors, int64_t n, int32_t j0,
+                                                         int32_t k, const int32_t *counts,
+                                                         int32_t *cursor, int32_t *perm) {
+  constexpr int ITEMS = 8;
+  __shared__ int off[32], cnt[32], base[32];
   const int j = blockIdx.y;
   if (threadIdx.x == 0) {
     int acc = 0;
@@ -567,13 +590,62 @@ __global__ void k_bucket_scatter(const uint8_t *colors, int64_t n, int32_t j0, i
       acc += counts[j * k + c];
     }
   }
-  __syncthreads();
   const uint8_t *col = colors + (int64_t)(j0 + j) * n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = col[i];
-    const int pos = atomicAdd(&cursor[j * k + c], 1);
-    perm[(int64_t)j * n + off[c] + pos] = (int32_t)i;
+  int32_t *out = perm + (int64_t)j * n;
+  for (int64_t t0 = (int64_t)blockIdx.x * BLOCK * ITEMS; t0 < n; t0 += (int64_t)gridDim.x * BLOCK * ITEMS) {
+    if (threadIdx.x < 32) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int c[ITEMS], pos[ITEMS];
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) {
+      const int64_t i = t0 + (int64_t)q * BLOCK + threadIdx.x;
+      c[q] = i < n ? (int)col[i] : -1;
+      pos[q] = c[q] >= 0 ? atomicAdd(&cnt[c[q]], 1) : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&cursor[j * k + threadIdx.x], cnt[threadIdx.x]) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) {
+      const int64_t i = t0 + (int64_t)q * BLOCK + threadIdx.x;
+      if (c[q] >= 0) out[off[c[q]] + base[c[q]] + pos[q]] = (int32_t)i;
+    }
+    __syncthreads();  // cnt and base are reused by the next tile
+  }
+}
+
+// Stage the columns idx[0..S) of R rows (row index -1: zeros) into LDS as
+// dst[r * lds + q] (times f[idx[q]] when SCALED), eight loads in flight per
+// thread.
+template <typename T, int R, bool SCALED>
+__device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t off, const int *rows,
+                                  const int32_t *__restrict__ idx, const float *__restrict__ f, int S,
+                                  T *__restrict__ dst, int lds) {
+  constexpr int U = 8;
+  const int total = R * S;
+  for (int x0 = threadIdx.x; x0 < total; x0 += U * BLOCK) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = x0 + u * BLOCK;
+      v[u] = T(0);
+      if (x < total) {
+        const int r = x / S, q = x - r * S;
+        if (rows[r] >= 0) {
+          const int col = idx[q];
+          v[u] = M[(int64_t)rows[r] * ld + off + col];
+          if constexpr (SCALED) v[u] *= f[col];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = x0 + u * BLOCK;
+      if (x < total) {
+        const int r = x / S, q = x - r * S;
+        dst[r * lds + q] = v[u];
+      }
+    }
   }
 }
 
@@ -582,7 +654,8 @@ __global__ void k_bucket_scatter(const uint8_t *colors, int64_t n, int32_t j0, i
 // without c and only pairs whose active set holds c contribute.  A block
 // takes R rows of one colour (rows grouped by colour), stages the active
 // columns holding c and the passive columns without c in LDS, and each thread
-// owns output columns holding c; the other output columns are written as 0.
+// owns output columns (in their natural order, so that whole lines are
+// written): columns holding c from their pairs, the others 0.
 template <typename T, int R, bool SCALED>
 __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   using A = Arith<T>;
@@ -622,40 +695,26 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
     __syncthreads();
     const int32_t *ca = a.ca + (int64_t)c * a.Sa;
     const int32_t *cb = a.cb + (int64_t)c * a.Sb;
-    for (int x = threadIdx.x; x < R * a.Sa; x += BLOCK) {
-      const int r = x / a.Sa, q = x - r * a.Sa;
-      T v = T(0);
-      if (rows[r] >= 0) {
-        const int col = ca[q];
-        v = Ma[(int64_t)rows[r] * a.lda + (int64_t)j * a.Ca + col];
-        if constexpr (SCALED) v *= fa[col];
-      }
-      la[r * sa + q] = v;
-    }
-    for (int x = threadIdx.x; x < R * a.Sb; x += BLOCK) {
-      const int r = x / a.Sb, q = x - r * a.Sb;
-      T v = T(0);
-      if (rows[r] >= 0) {
-        const int col = cb[q];
-        v = Bt[(int64_t)rows[r] * a.ldb + (int64_t)j * a.Cb + col];
-        if constexpr (SCALED) v *= fb[col];
-      }
-      lb[r * sb + q] = v;
-    }
+    stage_cols<T, R, SCALED>(Ma, a.lda, (int64_t)j * a.Ca, rows, ca, fa, a.Sa, la, sa);
+    stage_cols<T, R, SCALED>(Bt, a.ldb, (int64_t)j * a.Cb, rows, cb, fb, a.Sb, lb, sb);
     __syncthreads();
+    // output columns in their natural order, so that each wave writes whole
+    // lines: columns holding c from their pairs, the others zero
     const uint32_t *cp = a.cp + (int64_t)c * a.Q * a.U;
-    const int32_t *co = a.co + (int64_t)c * a.U;
-    for (int u = threadIdx.x; u < a.U; u += BLOCK) {
+    const int32_t *cu = a.cu + (int64_t)c * a.Cs;
+    for (int C = threadIdx.x; C < a.Cs; C += BLOCK) {
+      const int u = cu[C];
       T acc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] = T(0);
-      for (int q = 0; q < a.Q; ++q) {
-        const uint32_t p = cp[(int64_t)q * a.U + u];
-        const int x = p & 0xFFFFu, y = p >> 16;
+      if (u >= 0) {
+        for (int q = 0; q < a.Q; ++q) {
+          const uint32_t p = cp[(int64_t)q * a.U + u];
+          const int x = p & 0xFFFFu, y = p >> 16;
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + x], lb[r * sb + y], acc[r], ovf);
+          for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + x], lb[r * sb + y], acc[r], ovf);
+        }
       }
-      const int C = co[u];
       float m = 0.f;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -665,13 +724,9 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
         }
       }
       if constexpr (SCALED) {
-        if (m > 0.f) atomicMax(&lmx[C], __float_as_uint(m));
+        // column C belongs to this thread in every tile
+        if (m > 0.f && m > __uint_as_float(lmx[C])) lmx[C] = __float_as_uint(m);
       }
-    }
-    const int32_t *cz = a.cz + (int64_t)c * a.Z;
-    for (int x = threadIdx.x; x < R * a.Z; x += BLOCK) {
-      const int r = x / a.Z, v = x - r * a.Z;
-      if (rows[r] >= 0) Ms[(int64_t)rows[r] * a.lds + (int64_t)j * a.Cs + cz[v]] = T(0);
     }
   }
   if constexpr (is_u64<T>) {
@@ -711,17 +766,36 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
     const int64_t i = i0 + rsub;
     if (rsub >= rpi || i >= a.n) continue;
     const int c = col[i];
-    const T *brow = Bt + i * a.ldb + (int64_t)j * a.Cb;
-    for (int C = c0; C < a.Cs; C += cstep) {
-      const int idx = a.drop[(int64_t)c * a.Cs + C];
-      T v = T(0);
-      if (idx >= 0) {
-        v = brow[idx];
-        if constexpr (SCALED) v *= fb[idx];
+    const T *__restrict__ brow = Bt + i * a.ldb + (int64_t)j * a.Cb;
+    T *__restrict__ orow = Ms + i * a.lds + (int64_t)j * a.Cs;
+    const int32_t *__restrict__ drop = a.drop + (int64_t)c * a.Cs;
+    // eight columns in flight per thread
+    constexpr int U = 8;
+    for (int C0 = c0; C0 < a.Cs; C0 += U * cstep) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int C = C0 + u * cstep;
+        const int idx = C < a.Cs ? drop[C] : -1;
+        v[u] = T(0);
+        if (idx >= 0) {
+          v[u] = brow[idx];
+          if constexpr (SCALED) v[u] *= fb[idx];
+        }
       }
-      Ms[i * a.lds + (int64_t)j * a.Cs + C] = v;
-      if constexpr (SCALED) {
-        if ((float)v > 0.f) atomicMax((unsigned *)&lmx[C], __float_as_uint((float)v));
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int C = C0 + u * cstep;
+        if (C < a.Cs) {
+          orow[C] = v[u];
+          if constexpr (SCALED) {
+            if ((float)v[u] > 0.f) {
+              // one row per iteration: column C belongs to this thread
+              if (rpi == 1) lmx[C] = fmaxf(lmx[C], (float)v[u]);
+              else atomicMax((unsigned *)&lmx[C], __float_as_uint((float)v[u]));
+            }
+          }
+        }
       }
     }
   }
@@ -1151,7 +1225,8 @@ void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int3
   k_fill_u32<<<grid_cap((2 * b * k + BLOCK - 1) / BLOCK, 64), BLOCK, 0, s>>>((unsigned *)counts, (int64_t)b * k, 0u);
   k_fill_u32<<<grid_cap((2 * b * k + BLOCK - 1) / BLOCK, 64), BLOCK, 0, s>>>((unsigned *)cursor, (int64_t)b * k, 0u);
   k_bucket_count<<<dim3(g, b), BLOCK, 0, s>>>(colors, n, j0, k, counts);
-  k_bucket_scatter<<<dim3(g, b), BLOCK, 0, s>>>(colors, n, j0, k, counts, cursor, perm);
+  k_bucket_scatter<<<dim3(grid_cap((n + 8 * BLOCK - 1) / (8 * BLOCK), 1024), b), BLOCK, 0, s>>>(
+      colors, n, j0, k, counts, cursor, perm);
 }
 
 template <typename T, bool SC>

@@ -19,6 +19,14 @@ struct HistArgs {
   int32_t b;             // colourings in the pass
   void *H;               // n x ldh
   int64_t ldh;
+  // SpMM tasks (rows or segments of long rows); segments write their slot
+  // of `partial` (n_slots x ldh)
+  const int32_t *task_row;
+  const int64_t *task_beg;
+  const int32_t *task_len;
+  const int32_t *task_slot;
+  int64_t n_tasks;
+  void *partial;
 };
 
 struct SpmmArgs {
@@ -128,6 +136,7 @@ struct EmaColourArgs {
   int32_t Cs;
   const int32_t *ca, *cb, *co, *cz;  // [k][Sa], [k][Sb], [k][U], [k][Z]
   const uint32_t *cp;                // [k][Q][U]
+  const int32_t *cu;                 // [k][Cs]: u of an output column holding c, else -1
   int32_t Sa, Sb, U, Z, Q, k;
   const int32_t *perm;    // [b][n] rows grouped by colour
   const int32_t *counts;  // [b][k] rows per colour

@@ -546,6 +546,12 @@ sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) 
     blk.insert(blk.end(), nd.co.begin(), nd.co.end());
     blk.insert(blk.end(), nd.cz.begin(), nd.cz.end());
     blk.insert(blk.end(), nd.cp.begin(), nd.cp.end());
+    // inverse of co: output column -> its position among the columns holding c
+    const size_t cu0 = blk.size();
+    blk.resize(cu0 + (size_t)P.k * nd.cols, 0xFFFFFFFFu);
+    for (int c = 0; c < P.k; ++c)
+      for (int64_t u = 0; u < nd.c_u; ++u)
+        blk[cu0 + (size_t)c * nd.cols + nd.co[(size_t)c * nd.c_u + u]] = (uint32_t)u;
     ST_TRY(upload(blk, &D.cpr[i], s));
   }
   if (!P.root_list.empty()) {
@@ -718,7 +724,7 @@ void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots,
   }
   int64_t widest = 0;
   for (size_t s = 0; s < nn; ++s)
-    if (pp.B[s].last >= 0 && P.nodes[s].size > 1) widest = std::max(widest, pp.B[s].ld);
+    if (pp.B[s].last >= 0) widest = std::max(widest, pp.B[s].ld);  // the histogram too
   pp.partial_off = top;
   pp.partial_bytes = round_up(std::max<int64_t>(n_slots, 1) * std::max<int64_t>(widest, 1) * es, 256);
   pp.arena = top + pp.partial_bytes;
@@ -787,13 +793,37 @@ sg2v_status step_hist(Ctx &x, int node) {
   a.b = x.b;
   a.H = H.p;
   a.ldh = H.ld;
-  const int64_t blocks = std::min<int64_t>((x.g->n + 3) / 4, 4096);
+  a.task_row = x.g->task_row;
+  a.task_beg = x.g->task_beg;
+  a.task_len = x.g->task_len;
+  a.task_slot = x.g->task_slot;
+  a.n_tasks = x.g->n_tasks;
+  a.partial = (char *)x.ws->arena.p + x.pp.partial_off;
+  const int64_t blocks = std::min<int64_t>((x.g->n_tasks + 3) / 4, 8192);  // 4 waves per block
   {
     const double nnz = (double)x.g->nnz;
     ProfScope ps(SG2V_K_HIST,
                  nnz * (4.0 + (x.g->w ? 4.0 : 0.0) + x.b) + (double)x.g->n * (8.0 + x.b * x.P->k * x.es),
                  nnz * x.b, x.s);
     launch_hist(x.dt, a, (int)std::max<int64_t>(blocks, 1), x.s);
+  }
+  if (x.g->n_long > 0) {
+    // segments of long rows, summed in slot order
+    CombineArgs cb{};
+    cb.partial = a.partial;
+    cb.B = H.p;
+    cb.ld = H.ld;
+    cb.ncols_valid = H.cols * x.b;
+    cb.long_row = x.g->long_row;
+    cb.long_slot0 = x.g->long_slot0;
+    cb.long_nslot = x.g->long_nslot;
+    cb.n_long = x.g->n_long;
+    cb.mx = nullptr;
+    cb.ovf = x.ovf;
+    cb.accumulate = 0;
+    ProfScope ps(SG2V_K_SPMM_COMBINE, (double)(x.g->n_slots + x.g->n_long) * H.ld * x.es,
+                 (double)x.g->n_slots * H.ld, x.s);
+    launch_spmm_combine(x.dt, cb, x.s);
   }
   if (x.dt == DT_U64) launch_zero_pad(x.dt, H.p, x.g->n, H.ld, H.cols * x.b, x.s);
   if (x.dt == DT_F32) {
@@ -1069,6 +1099,7 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
   a.co = a.cb + (size_t)k * nd.c_sb;
   a.cz = a.co + (size_t)k * nd.c_u;
   a.cp = (const uint32_t *)(a.cz + (size_t)k * nd.c_z);
+  a.cu = (const int32_t *)(a.cp + (size_t)k * nd.c_q * nd.c_u);
   a.Sa = (int32_t)nd.c_sa;
   a.Sb = (int32_t)nd.c_sb;
   a.U = (int32_t)nd.c_u;
