@@ -497,12 +497,23 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
       T acc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] = T(0);
-      for (int q = 0; q < a.np; ++q) {
-        const int2 p = pairs[(int64_t)q * a.Cs + C];
-        if constexpr (STAGE) {
+      if constexpr (STAGE) {
+        // eight pair indices in flight
+        for (int q0 = 0; q0 < a.np; q0 += 8) {
+          int2 pp[8];
 #pragma unroll
-          for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + p.x], lb[r * sb + p.y], acc[r], ovf);
-        } else {
+          for (int qq = 0; qq < 8; ++qq) pp[qq] = pairs[(int64_t)min(q0 + qq, a.np - 1) * a.Cs + C];
+#pragma unroll
+          for (int qq = 0; qq < 8; ++qq) {
+            if (q0 + qq >= a.np) break;  // uniform
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + pp[qq].x], lb[r * sb + pp[qq].y], acc[r], ovf);
+          }
+        }
+      }
+      for (int q = 0; q < (STAGE ? 0 : a.np); ++q) {
+        const int2 p = pairs[(int64_t)q * a.Cs + C];
+        {
           T sxa = T(1), sxb = T(1);
           if constexpr (SCALED) {
             sxa = fa[p.x];
@@ -624,26 +635,29 @@ __device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t o
   constexpr int U = 8;
   const int total = R * S;
   for (int x0 = threadIdx.x; x0 < total; x0 += U * BLOCK) {
-    T v[U];
+    // every load is issued (indices clamped into range) before any is used
+    int rr[U], q[U], col[U], row[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int x = x0 + u * BLOCK;
-      v[u] = T(0);
-      if (x < total) {
-        const int r = x / S, q = x - r * S;
-        if (rows[r] >= 0) {
-          const int col = idx[q];
-          v[u] = M[(int64_t)rows[r] * ld + off + col];
-          if constexpr (SCALED) v[u] *= f[col];
-        }
-      }
+      const int x = min(x0 + u * BLOCK, total - 1);
+      rr[u] = x / S;
+      q[u] = x - rr[u] * S;
+      col[u] = idx[q[u]];
+      row[u] = rows[rr[u]];
+    }
+    T v[U];
+    float fv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = M[(int64_t)max(row[u], 0) * ld + off + col[u]];
+      fv[u] = SCALED ? f[col[u]] : 1.0f;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int x = x0 + u * BLOCK;
-      if (x < total) {
-        const int r = x / S, q = x - r * S;
-        dst[r * lds + q] = v[u];
+      if (x0 + u * BLOCK < total) {
+        T w = row[u] >= 0 ? v[u] : T(0);
+        if constexpr (SCALED) w *= fv[u];
+        dst[rr[u] * lds + q[u]] = w;
       }
     }
   }
@@ -708,11 +722,18 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] = T(0);
       if (u >= 0) {
-        for (int q = 0; q < a.Q; ++q) {
-          const uint32_t p = cp[(int64_t)q * a.U + u];
-          const int x = p & 0xFFFFu, y = p >> 16;
+        // eight pair indices in flight
+        for (int q0 = 0; q0 < a.Q; q0 += 8) {
+          uint32_t p[8];
 #pragma unroll
-          for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + x], lb[r * sb + y], acc[r], ovf);
+          for (int qq = 0; qq < 8; ++qq) p[qq] = cp[(int64_t)min(q0 + qq, a.Q - 1) * a.U + u];
+#pragma unroll
+          for (int qq = 0; qq < 8; ++qq) {
+            if (q0 + qq >= a.Q) break;  // uniform
+            const int x = p[qq] & 0xFFFFu, y = p[qq] >> 16;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + x], lb[r * sb + y], acc[r], ovf);
+          }
         }
       }
       float m = 0.f;
@@ -916,10 +937,18 @@ __global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
     const int c = col[i];
     const uint32_t *lc = a.list16 + (int64_t)c * a.L;
     T s = T(0);
-    for (int64_t q = threadIdx.x; q < a.L; q += BLOCK) {
-      const uint32_t p = lc[q];
-      if constexpr (HASY) s = A::fma(lx[p & 0xFFFFu], ly[p >> 16], s, ovf);
-      else s = A::add(s, lx[p & 0xFFFFu], ovf);
+    // eight list entries in flight per thread
+    for (int64_t q0 = threadIdx.x; q0 < a.L; q0 += 8 * BLOCK) {
+      uint32_t p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = lc[min<int64_t>(q0 + u * BLOCK, a.L - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (q0 + u * BLOCK < a.L) {
+          if constexpr (HASY) s = A::fma(lx[p[u] & 0xFFFFu], ly[p[u] >> 16], s, ovf);
+          else s = A::add(s, lx[p[u] & 0xFFFFu], ovf);
+        }
+      }
     }
     for (int off = 1; off < WAVE; off <<= 1) s = A::add(s, shfl_xor(s, off), ovf);
     if (lane == 0) red[wv] = s;
