@@ -625,13 +625,13 @@ __global__ void __launch_bounds__(BLOCK) k_bucket_scatter(const uint8_t *colors,
   }
 }
 
-// Stage the columns idx[0..S) of R rows (row index -1: zeros) into LDS as
-// dst[r * lds + q] (times f[idx[q]] when SCALED), eight loads in flight per
-// thread.
+// Stage the columns idx[0..S) of R rows (row index -1: zeros) into LDS
+// transposed, dst[q * RP + r] (times f[idx[q]] when SCALED), eight loads in
+// flight per thread.
 template <typename T, int R, bool SCALED>
 __device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t off, const int *rows,
                                   const int32_t *__restrict__ idx, const float *__restrict__ f, int S,
-                                  T *__restrict__ dst, int lds) {
+                                  T *__restrict__ dst, int RP) {
   constexpr int U = 8;
   const int total = R * S;
   for (int x0 = threadIdx.x; x0 < total; x0 += U * BLOCK) {
@@ -657,7 +657,7 @@ __device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t o
       if (x0 + u * BLOCK < total) {
         T w = row[u] >= 0 ? v[u] : T(0);
         if constexpr (SCALED) w *= fv[u];
-        dst[rr[u] * lds + q[u]] = w;
+        dst[q[u] * RP + rr[u]] = w;
       }
     }
   }
@@ -673,13 +673,22 @@ __device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t o
 template <typename T, int R, bool SCALED>
 __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   using A = Arith<T>;
+  constexpr int N = V16<T>::N;
+  // staged columns are R rows long, padded by one 16-byte vector so that
+  // lanes reading different columns spread over the LDS banks
+  constexpr int RP = R + N;
+  static_assert(R % N == 0, "R");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int rows[R];
   const int j = blockIdx.y;
-  const int sa = a.Sa | 1, sb = a.Sb | 1;
+  // la holds one extra all-zero column (index Sa) that pads the pair lists
   T *la = (T *)smem;
-  T *lb = la + R * sa;
-  unsigned *lmx = (unsigned *)(lb + R * sb);
+  T *lb = la + (int64_t)RP * (a.Sa + 1);
+  // FP32S column maxima of the block, kept as exponent codes: 0 for no
+  // positive value, else the float's exponent field + 1 (what the frame
+  // exponent needs is floor(log2 max), which the code determines exactly)
+  uint8_t *lmx = (uint8_t *)(lb + (int64_t)RP * a.Sb);
+  for (int r = threadIdx.x; r < RP; r += BLOCK) la[(int64_t)a.Sa * RP + r] = T(0);
   const T *Ma = (const T *)a.Ma;
   const T *Bt = (const T *)a.B;
   T *Ms = (T *)a.Ms;
@@ -688,7 +697,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   const int32_t *cnt = a.counts + (int64_t)j * a.k;
   bool ovf = false;
   if (SCALED)
-    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0u;
+    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0;
   int64_t ntiles = 0;
   for (int c = 0; c < a.k; ++c) ntiles += (cnt[c] + R - 1) / R;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -709,8 +718,8 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
     __syncthreads();
     const int32_t *ca = a.ca + (int64_t)c * a.Sa;
     const int32_t *cb = a.cb + (int64_t)c * a.Sb;
-    stage_cols<T, R, SCALED>(Ma, a.lda, (int64_t)j * a.Ca, rows, ca, fa, a.Sa, la, sa);
-    stage_cols<T, R, SCALED>(Bt, a.ldb, (int64_t)j * a.Cb, rows, cb, fb, a.Sb, lb, sb);
+    stage_cols<T, R, SCALED>(Ma, a.lda, (int64_t)j * a.Ca, rows, ca, fa, a.Sa, la, RP);
+    stage_cols<T, R, SCALED>(Bt, a.ldb, (int64_t)j * a.Cb, rows, cb, fb, a.Sb, lb, RP);
     __syncthreads();
     // output columns in their natural order, so that each wave writes whole
     // lines: columns holding c from their pairs, the others zero
@@ -724,15 +733,21 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
       if (u >= 0) {
         // eight pair indices in flight
         for (int q0 = 0; q0 < a.Q; q0 += 8) {
+          // past the end of the list: the zero column, which adds nothing
           uint32_t p[8];
 #pragma unroll
-          for (int qq = 0; qq < 8; ++qq) p[qq] = cp[(int64_t)min(q0 + qq, a.Q - 1) * a.U + u];
+          for (int qq = 0; qq < 8; ++qq)
+            p[qq] = q0 + qq < a.Q ? cp[(int64_t)(q0 + qq) * a.U + u] : (uint32_t)a.Sa;
 #pragma unroll
           for (int qq = 0; qq < 8; ++qq) {
-            if (q0 + qq >= a.Q) break;  // uniform
-            const int x = p[qq] & 0xFFFFu, y = p[qq] >> 16;
+            const V16<T> *xa = (const V16<T> *)(la + (int)(p[qq] & 0xFFFFu) * RP);
+            const V16<T> *yb = (const V16<T> *)(lb + (int)(p[qq] >> 16) * RP);
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = A::fma(la[r * sa + x], lb[r * sb + y], acc[r], ovf);
+            for (int v = 0; v < R / N; ++v) {
+              const V16<T> xv = xa[v], yv = yb[v];
+#pragma unroll
+              for (int e = 0; e < N; ++e) acc[v * N + e] = A::fma(xv.x[e], yv.x[e], acc[v * N + e], ovf);
+            }
           }
         }
       }
@@ -746,7 +761,8 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
       }
       if constexpr (SCALED) {
         // column C belongs to this thread in every tile
-        if (m > 0.f && m > __uint_as_float(lmx[C])) lmx[C] = __float_as_uint(m);
+        const uint32_t code = m > 0.f ? (__float_as_uint(m) >> 23) + 1u : 0u;
+        if (code > lmx[C]) lmx[C] = (uint8_t)code;
       }
     }
   }
@@ -756,7 +772,10 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   if constexpr (SCALED) {
     __syncthreads();
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
-      if (lmx[c]) atomicMax(a.mx + (int64_t)j * a.Cs + c, lmx[c]);
+      // a float with the same floor(log2): 2^(field - 127), or the smallest
+      // subnormal for a subnormal maximum
+      const uint32_t code = lmx[c];
+      if (code) atomicMax(a.mx + (int64_t)j * a.Cs + c, code == 1u ? 1u : (code - 1u) << 23);
       if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
     }
   }
@@ -1265,7 +1284,6 @@ static int ema_colour_t(const EmaColourArgs &a, int R, dim3 grid, size_t lds, hi
     kern<<<grid, BLOCK, lds, s>>>(a);
   };
   switch (R) {
-    case 2: go(k_ema_colour<T, 2, SC>); return 0;
     case 4: go(k_ema_colour<T, 4, SC>); return 0;
     case 8: go(k_ema_colour<T, 8, SC>); return 0;
     case 16: go(k_ema_colour<T, 16, SC>); return 0;

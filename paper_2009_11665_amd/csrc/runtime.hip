@@ -1117,14 +1117,18 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
   a.es = g.es;
   a.ovf = g.ovf;
   const bool sc = x.dt == DT_F32;
-  const size_t lmx = sc ? (size_t)nd.cols * 4 : 0;
+  const size_t lmx = sc ? (size_t)round_up(nd.cols, 16) : 0;  // one byte per output column
   const size_t budget = std::min<size_t>(x.lds_max, 80 * 1024);
-  const size_t rowb = (size_t)((a.Sa | 1) + (a.Sb | 1)) * x.es;
+  // staged columns hold R rows plus one 16-byte vector of padding
+  const int Nv = 16 / (int)x.es;
+  auto lds_for = [&](int R) { return (size_t)(a.Sa + 1 + a.Sb) * (R + Nv) * x.es + lmx; };
   sg2v_tuning_t tu = tuning();
-  int R = tu.ema_rows > 0 ? std::min(tu.ema_rows, 16) : 16;
-  while (R > 2 && R * rowb + lmx > budget) R /= 2;
-  if (R < 2) R = 2;
-  const size_t lds = R * rowb + lmx;
+  int R = 16;
+  if (tu.ema_rows > 0)
+    while (R > 4 && R > tu.ema_rows) R /= 2;  // a power of two, 4..16
+  while (R > 4 && lds_for(R) > budget) R /= 2;
+  if (R < 4) R = 4;
+  const size_t lds = lds_for(R);
   if (lds > x.lds_max) {
     set_error("sg2v_count: colour-restricted eMA needs %zu bytes of LDS", lds);
     return SG2V_ERANGE;
