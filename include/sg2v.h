@@ -244,6 +244,8 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
 #define SG2V_TUNE_FORCE_XSPLIT 16 /* split even when a chunk fits the caches (tests) */
 #define SG2V_TUNE_XSPLIT 32      /* split long SpMM tasks over the XCDs' neighbour ranges when one
                                     column chunk of the gathered table exceeds 32 MB (off by default) */
+#define SG2V_TUNE_ROOT_ROWS 64   /* root reduction one vertex per block step in vertex order instead
+                                    of colour by colour with double-buffered rows */
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;

@@ -322,6 +322,7 @@ TUNE_SPMM_UNROLL4 = 4
 TUNE_NO_XSPLIT = 8
 TUNE_FORCE_XSPLIT = 16
 TUNE_XSPLIT = 32
+TUNE_ROOT_ROWS = 64
 
 
 def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,

@@ -985,6 +985,136 @@ __global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
   }
 }
 
+// Root reduction, colour by colour: block b takes the contiguous vertex
+// range [b n / gridDim.x, (b + 1) n / gridDim.x) and, for each colour c in
+// turn, lists the range's vertices of colour c (in vertex order) and walks
+// them with c's (x, y) list held in registers (LPT entries per thread).
+// Rows (one table: Y is X or absent) are staged in LDS double-buffered with
+// 16-byte loads: the next row's loads are in flight while the current row
+// is summed; the column factors stay in registers.  Each thread accumulates
+// its share of every vertex's terms (summed per vertex in T) in double
+// (uint64 in U64); the block then reduces its threads in a fixed order.
+// Needs Cx <= PV * N * BLOCK, L <= LPT * BLOCK and 16-byte aligned rows.
+template <typename T, bool SCALED, bool HASY, int LPT, int PV>
+__global__ void __launch_bounds__(BLOCK) k_root_tile(RootArgs a) {
+  using A = Arith<T>;
+  using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
+  constexpr int N = V16<T>::N;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int rowlist[BLOCK];
+  __shared__ int wcount[WAVES_PER_BLOCK];
+  __shared__ Acc red[WAVES_PER_BLOCK];
+  const int nvec = (a.Cx + N - 1) / N;
+  T *lx0 = (T *)smem;
+  T *lx1 = lx0 + (int64_t)nvec * N;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int j = blockIdx.y;
+  const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
+  const T *X = (const T *)a.X;
+  const int64_t r0 = (int64_t)blockIdx.x * a.n / gridDim.x;
+  const int64_t r1 = (int64_t)(blockIdx.x + 1) * a.n / gridDim.x;
+  bool ovf = false;
+  Acc tot = Acc(0);
+  // column factors of this thread's vectors
+  float f[PV][N];
+#pragma unroll
+  for (int u = 0; u < PV; ++u) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+      const int c = (threadIdx.x + u * BLOCK) * N + e;
+      f[u][e] = 1.0f;
+      if constexpr (SCALED) f[u][e] = c < a.Cx ? a.fx[(int64_t)j * a.Cx + c] : 0.0f;
+    }
+  }
+  V16<T> v[PV];
+  auto fetch = [&](int64_t i) {
+    const V16<T> *xr = (const V16<T> *)(X + i * a.ldx + (int64_t)j * a.Cx);
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int q = threadIdx.x + u * BLOCK;
+      if (q < nvec) v[u] = xr[q];
+    }
+  };
+  auto store = [&](T *lx) {
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int q = threadIdx.x + u * BLOCK;
+      if (q < nvec) {
+        V16<T> w = v[u];
+        if constexpr (SCALED) {
+#pragma unroll
+          for (int e = 0; e < N; ++e) w.x[e] *= f[u][e];
+        }
+        ((V16<T> *)lx)[q] = w;
+      }
+    }
+  };
+  for (int c = 0; c < a.k; ++c) {
+    // this colour's (x, y) pairs, LPT per thread
+    const uint32_t *lc = a.list16 + (int64_t)c * a.L;
+    uint32_t p[LPT];
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int64_t q = threadIdx.x + (int64_t)u * BLOCK;
+      p[u] = q < a.L ? lc[q] : 0u;
+    }
+    for (int64_t base = r0; base < r1; base += BLOCK) {
+      // the chunk's vertices of colour c, in vertex order
+      const int64_t i = base + threadIdx.x;
+      const bool hit = i < r1 && col[i] == c;
+      const uint64_t m = __ballot(hit);
+      __syncthreads();  // rowlist and the row buffers are free again
+      if (lane == 0) wcount[wv] = __popcll(m);
+      __syncthreads();
+      int pos = __popcll(m & ((1ull << lane) - 1ull)), cnt = 0;
+      for (int w = 0; w < WAVES_PER_BLOCK; ++w) {
+        if (w < wv) pos += wcount[w];
+        cnt += wcount[w];
+      }
+      if (hit) rowlist[pos] = (int)i;
+      __syncthreads();
+      if (cnt == 0) continue;
+      fetch(rowlist[0]);
+      for (int t = 0; t < cnt; ++t) {
+        T *lx = (t & 1) ? lx1 : lx0;
+        store(lx);
+        __syncthreads();
+        if (t + 1 < cnt) fetch(rowlist[t + 1]);  // in flight during the sum
+        T s = T(0);
+#pragma unroll
+        for (int u = 0; u < LPT; ++u) {
+          if (threadIdx.x + u * BLOCK < a.L) {
+            if constexpr (HASY) s = A::fma(lx[p[u] & 0xFFFFu], lx[p[u] >> 16], s, ovf);
+            else s = A::add(s, lx[p[u] & 0xFFFFu], ovf);
+          }
+        }
+        if constexpr (is_u64<Acc>) tot = A::add(tot, s, ovf);
+        else tot += (double)s;
+      }
+    }
+  }
+  // fixed-order block reduction
+  for (int off = 1; off < WAVE; off <<= 1) {
+    if constexpr (is_u64<Acc>) tot = A::add(tot, shfl_xor(tot, off), ovf);
+    else tot += shfl_xor(tot, off);
+  }
+  __syncthreads();
+  if (lane == 0) red[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Acc b = red[0];
+    for (int q = 1; q < WAVES_PER_BLOCK; ++q) {
+      if constexpr (is_u64<Acc>) b = A::add(b, red[q], ovf);
+      else b += red[q];
+    }
+    ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = b;
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+}
+
 template <typename Acc>
 __global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1245,6 +1375,21 @@ static void root_lds_t(const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) 
   auto kern = a.Y ? k1 : k0;
   if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   kern<<<grid, BLOCK, lds, s>>>(a);
+}
+
+template <typename T, bool SC>
+static void root_tile_t(const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+  auto k1 = k_root_tile<T, SC, true, 16, 8>;
+  auto k0 = k_root_tile<T, SC, false, 16, 8>;
+  auto kern = a.Y ? k1 : k0;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kern<<<grid, BLOCK, lds, s>>>(a);
+}
+
+void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+  if (dtype == DT_F32) root_tile_t<float, true>(a, grid, lds, s);
+  else if (dtype == DT_F64) root_tile_t<double, false>(a, grid, lds, s);
+  else root_tile_t<uint64_t, false>(a, grid, lds, s);
 }
 
 void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {

@@ -188,6 +188,7 @@ struct RootArgs {
   int *ovf;
   const uint32_t *list16;  // nullable: (x | y << 16) [k][L], y = 0xFFFF for Y = 1
   int32_t same_xy;         // X and Y are the same table (staged once)
+  int32_t k;               // colours (root lists per colour)
 };
 
 void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
@@ -205,6 +206,10 @@ void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipSt
 void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
 // block per vertex row, rows staged in LDS; lds = bytes of the staged rows
 void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
+// colour by colour over contiguous vertex ranges; needs list16, k, Y = X or
+// absent, L <= 4096, Cx <= 8 * 256 * (16 / element size), 16-byte aligned
+// rows, and lds = 2 * Cx (rounded up to 16 bytes) * element size
+void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s);
 void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,

@@ -55,6 +55,7 @@ sg2v_tuning_t tuning() {
 
 constexpr int64_t kSegment = 4096;  // neighbours per SpMM task (longer rows are split)
 constexpr int kPersistBlocks = 2048;
+constexpr int kRootBlocks = 2048;    // most root blocks (per-block partial sums)
 constexpr int kXsplit = 8;          // neighbour ranges (one per XCD)
 constexpr int64_t kXsplitMin = 128; // tasks at least this long are split by range
 
@@ -1251,18 +1252,29 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
     a.fx = X->f;
     a.fy = Y ? Y->f : nullptr;
   }
-  const int nblk = 1024;
   a.partial = x.ws->partial.p;
   a.ovf = x.ovf;
   a.list16 = x.dp.root_list16;
   a.same_xy = Y && Y->p == X->p;
+  a.k = P.k;
   const size_t stage = (size_t)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es;
   const bool use_lds = a.list16 && stage <= std::min<size_t>(x.lds_max, 64 * 1024);
+  // colour by colour, double-buffered rows, lists in registers
+  const int64_t Nv = 16 / x.es;
+  const size_t tile_lds = 2 * (size_t)round_up(X->cols, Nv) * x.es;
+  const bool aligned = x.b == 1 || (X->cols * x.es) % 16 == 0;
+  const bool use_tile = use_lds && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && (!Y || a.same_xy) &&
+                        aligned && P.root_L <= 16 * 256 && X->cols <= 8 * 256 * Nv && tile_lds <= 64 * 1024;
+  int nblk = 1024;
+  if (use_tile)
+    nblk = (int)std::min<int64_t>(kRootBlocks, (int64_t)x.cu_count *
+                                                   std::max<int64_t>(1, (int64_t)(x.lds_max / tile_lds)));
   {
     ProfScope ps(SG2V_K_ROOT,
                  (double)x.g->n * x.b * (double)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es,
                  (double)x.g->n * x.b * (double)P.root_L, x.s);
-    if (use_lds) launch_root_lds(x.dt, a, dim3(nblk, x.b), stage, x.s);
+    if (use_tile) launch_root_tile(x.dt, a, dim3(nblk, x.b), tile_lds, x.s);
+    else if (use_lds) launch_root_lds(x.dt, a, dim3(nblk, x.b), stage, x.s);
     else launch_root(x.dt, a, dim3(nblk, x.b), x.s);
   }
   const int es = 8;
@@ -1409,7 +1421,7 @@ sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_col
   }
   ST_TRY(x.ws->arena.ensure(x.pp.arena));
   ST_TRY(x.ws->small.ensure(x.pp.small_bytes));
-  ST_TRY(x.ws->partial.ensure((size_t)1024 * b * 8));
+  ST_TRY(x.ws->partial.ensure((size_t)kRootBlocks * b * 8));
   ST_TRY(x.ws->ovf.ensure(256));
   ST_TRY(x.ws->bucket.ensure((size_t)b * (64 + g->n) * 4 + 256));
   if (!(tuning().flags & SG2V_TUNE_NO_COLOR_SKIP))

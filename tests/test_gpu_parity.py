@@ -211,7 +211,7 @@ def test_spmm_widths_agree(small_rmat):
             for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA, sg.TUNE_SPMM_UNROLL4,
                        sg.TUNE_FORCE_XSPLIT, sg.TUNE_FORCE_XSPLIT | sg.TUNE_NO_COLOR_SKIP,
                        sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA | sg.TUNE_SPMM_UNROLL4,
-                       sg.TUNE_XSPLIT):
+                       sg.TUNE_XSPLIT, sg.TUNE_ROOT_ROWS):
                 sg.set_tuning(spmm_width=w, flags=fl)
                 say("spmm width", w, "flags", fl)
                 got = sg.count(p, g, c, "u64")["colorful_u64"]
@@ -313,3 +313,24 @@ def test_bintree15_on_rmat14_against_oracle():
     assert ref[0][0] > 0
     assert r64["colorful"][0] == pytest.approx(ref[0][0], rel=FP64_TOL)
     assert r32["colorful"][0] == pytest.approx(ref[0][0], rel=FP32_TOL)
+
+
+@pytest.mark.parametrize("flags", [0, 64])
+def test_bintree15_u64_exact_both_root_paths(flags):
+    """Exact (mod 2^64) count of the 15-vertex binary tree, root reduced colour
+    by colour over vertex ranges (flags 0) and one vertex per block step
+    (flags 64), against the oracle's exact mode."""
+    G = gg.rmat(11, 25_000, seed=8)
+    par, k = gg.BINTREE15, 15
+    ref = [x[1] for x in oracle_counts(G, par, k, 9, 2, O.U64)]  # mod 2^64
+    ref64 = [x[0] for x in oracle_counts(G, par, k, 9, 2, O.FP64)]
+    old = sg.get_tuning()
+    sg.set_tuning(flags=flags)
+    try:
+        r = gpu_counts(G, par, k, 9, 2, "u64")
+        r32 = gpu_counts(G, par, k, 9, 2, "fp32s")
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+    say("bt15 u64", flags, ref, list(r["colorful_u64"]))
+    assert [int(x) for x in r["colorful_u64"]] == ref
+    np.testing.assert_allclose(r32["colorful"], ref64, rtol=FP32_TOL)
