@@ -57,7 +57,10 @@ constexpr int64_t kSegment = 4096;  // neighbours per SpMM task (longer rows are
 constexpr int kPersistBlocks = 2048;
 constexpr int kRootBlocks = 2048;    // most root blocks (per-block partial sums)
 constexpr int kXsplit = 8;          // neighbour ranges (one per XCD)
-constexpr int64_t kXsplitMin = 128; // tasks at least this long are split by range
+constexpr int64_t kXsplitMin = 512; // tasks at least this long are split by range
+// graphs whose 128-byte column chunk (n rows) reaches 32 MB: wider chunks and
+// the neighbour-range split by default
+bool large_graph(int64_t n) { return (double)n * 128.0 >= 32.0 * (1 << 20); }
 
 int dtype_of(sg2v_mode m) { return m == SG2V_FP32S ? DT_F32 : (m == SG2V_FP64 ? DT_F64 : DT_U64); }
 int esize_of(int dt) { return dt == DT_F32 ? 4 : 8; }
@@ -617,11 +620,15 @@ Workspace &workspace() {
   return *p;
 }
 
-int pick_G(int dt, int64_t widest_cols_b) {
+// Lanes per row segment of the SpMM (chunk width G * N columns).  Automatic:
+// 128-byte segments, or 256-byte segments (with the neighbour-range split of
+// long tasks, below) on graphs whose 128-byte column chunk reaches 32 MB.
+int pick_G(int dt, int64_t widest_cols_b, int64_t n) {
   sg2v_tuning_t tu = tuning();
   const int N = dt == DT_F32 ? 4 : 2;
   int G = 8;  // 128-byte row segments
   if (tu.spmm_width > 0) G = std::max(2, std::min(16, tu.spmm_width / N));
+  else if (large_graph(n) && !(tu.flags & SG2V_TUNE_NO_XSPLIT)) G = 16;
   // narrow tables: do not read far past the last column
   while (G > 2 && (int64_t)G * N / 2 >= widest_cols_b) G /= 2;
   int p2 = 2;
@@ -891,10 +898,11 @@ sg2v_status chunk_masks(Ctx &x, int node, int W, const int32_t **jb, const uint3
 // partial-row buffer exist.
 sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t *group) {
   *group = 0;
-  const int fl = tuning().flags;
+  const sg2v_tuning_t tu = tuning();
+  const int fl = tu.flags;
   if ((fl & SG2V_TUNE_NO_XSPLIT) || U->x_units == 0) return SG2V_OK;
-  if (!(fl & SG2V_TUNE_FORCE_XSPLIT) &&
-      (!(fl & SG2V_TUNE_XSPLIT) || (double)x.g->n * W * x.es < 32.0 * (1 << 20)))
+  const bool wanted = (fl & SG2V_TUNE_XSPLIT) || (tu.spmm_width == 0 && large_graph(x.g->n));
+  if (!(fl & SG2V_TUNE_FORCE_XSPLIT) && (!wanted || (double)x.g->n * W * x.es < 32.0 * (1 << 20)))
     return SG2V_OK;
   sg2v_graph *g = x.g;
   if (!g->tsplit) {
@@ -1263,8 +1271,8 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const int64_t Nv = 16 / x.es;
   const size_t tile_lds = 2 * (size_t)round_up(X->cols, Nv) * x.es;
   const bool aligned = x.b == 1 || (X->cols * x.es) % 16 == 0;
-  const bool use_tile = use_lds && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && (!Y || a.same_xy) &&
-                        aligned && P.root_L <= 16 * 256 && X->cols <= 8 * 256 * Nv && tile_lds <= 64 * 1024;
+  const bool use_tile = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && (!Y || a.same_xy) &&
+                        aligned && P.root_L <= 16 * 256 && X->cols <= 8 * 256 * Nv && tile_lds <= x.lds_max;
   int nblk = 1024;
   if (use_tile)
     nblk = (int)std::min<int64_t>(kRootBlocks, (int64_t)x.cu_count *
@@ -1377,7 +1385,7 @@ int choose_batch(const Plan &P, int ncol, int dt, int64_t n, int64_t n_slots) {
   int64_t budget = tu.budget_bytes > 0 ? tu.budget_bytes : (int64_t)(fr * 0.85);
   while (b > 1) {
     PassPlan pp;
-    build_pass(P, n, b, dt, pick_G(dt, widest_passive * b), n_slots, pp, PassOpts());
+    build_pass(P, n, b, dt, pick_G(dt, widest_passive * b, n), n_slots, pp, PassOpts());
     if (pp.arena <= budget) break;
     b = (b + 1) / 2;
   }
@@ -1412,7 +1420,7 @@ sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_col
   int64_t widest = 1;
   for (auto &nd : plan->p.nodes)
     if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? plan->p.k : nd.cols);
-  build_pass(plan->p, g->n, b, x.dt, pick_G(x.dt, widest * b), g->n_slots, x.pp, opt);
+  build_pass(plan->p, g->n, b, x.dt, pick_G(x.dt, widest * b, g->n), g->n_slots, x.pp, opt);
   sg2v_tuning_t tu = tuning();
   if (tu.budget_bytes > 0 && x.pp.arena > tu.budget_bytes) {
     set_error("sg2v_count: one colouring needs %lld bytes, budget is %lld",
@@ -1440,8 +1448,14 @@ sg2v_status prewarm(Ctx &x, int b) {
   build_pass(*x.P, x.g->n, b, x.dt, x.pp.G, x.g->n_slots, pp, PassOpts());
   UnitTable *U = nullptr;
   ST_TRY(build_units(x.g, x.pp.G, x.s, &U));
-  if (tuning().flags & SG2V_TUNE_NO_COLOR_SKIP) return SG2V_OK;
   const int W = x.pp.G * (x.dt == DT_F32 ? 4 : 2);
+  // split offsets and partial rows of the neighbour-range split
+  for (auto &st : pp.steps)
+    if (st.kind == S_SPMM) {
+      int64_t gch = 0;
+      ST_TRY(xsplit_setup(x, U, pp.M[st.node].cols * b, W, &gch));
+    }
+  if (tuning().flags & SG2V_TUNE_NO_COLOR_SKIP) return SG2V_OK;
   const int keep_b = x.b;
   x.b = b;
   for (auto &st : pp.steps)
@@ -1778,7 +1792,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
   int64_t widest = 1;
   for (auto &nd : P.nodes)
     if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? P.k : nd.cols);
-  const int G = pick_G(DT_F64, widest);
+  const int G = pick_G(DT_F64, widest, g->n);
   const int64_t align = std::max<int64_t>(16, (int64_t)G * 2);
   // adjoint tables of every node with more than one vertex, plus Bbar
   std::vector<int64_t> off(nn, -1), ld(nn, 0);
