@@ -73,14 +73,17 @@ def kernel_sha():
     return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(launches_per_colouring):
     """HBM bytes per SpMM launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+    were taken on the current kernel source with the same launches per
+    colouring (the launch configuration)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         d = json.load(f)
     if d.get("kernel_source_sha") != kernel_sha():
+        return None
+    if d.get("spmm_launches_per_colouring") != launches_per_colouring:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -118,6 +121,7 @@ def write_traffic(spmm_fetch, spmm_write, copy_fetch, copy_write, copy_mib):
     sw, nw = mean_of(spmm_write, "WRITE_SIZE", is_spmm)
     rd, wr = sf * 1024.0 * f_fetch, sw * 1024.0 * f_write
     out = {"kernel": "k_spmm<float,...>", "kernel_source_sha": kernel_sha(),
+           "spmm_launches_per_colouring": nf,
            "hbm_bytes_per_launch": rd + wr, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
            "launches": [nf, nw], "fetch_size_kib_per_launch": sf, "write_size_kib_per_launch": sw,
            "calibration": {"copy_bytes": nbytes, "fetch_factor": f_fetch, "write_factor": f_write},
@@ -264,7 +268,9 @@ def main():
 
     sp = prof["spmm"]
     achieved = sp["bytes"] / (sp["ms"] * 1e-3) / 1e9 if sp["ms"] > 0 else 0.0
-    traffic = load_traffic()  # measured HBM bytes per SpMM launch (rocprofv3 counters)
+    # measured HBM bytes per SpMM launch (rocprofv3 counters)
+    traffic = load_traffic(sp["launches"] // (args.steps * ncol) if sp["launches"] % (args.steps * ncol) == 0
+                           else None)
     total_bytes = sum(v["bytes"] for v in prof.values())
     kernels = {kk: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
                     "model_GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else 0.0}

@@ -1379,8 +1379,10 @@ static void root_lds_t(const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) 
 
 template <typename T, bool SC>
 static void root_tile_t(const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-  auto k1 = k_root_tile<T, SC, true, 16, 8>;
-  auto k0 = k_root_tile<T, SC, false, 16, 8>;
+  // 16-byte vectors per thread: rows of up to 8192 elements
+  constexpr int PV = sizeof(T) == 4 ? 8 : 16;
+  auto k1 = k_root_tile<T, SC, true, 16, PV>;
+  auto k0 = k_root_tile<T, SC, false, 16, PV>;
   auto kern = a.Y ? k1 : k0;
   if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   kern<<<grid, BLOCK, lds, s>>>(a);

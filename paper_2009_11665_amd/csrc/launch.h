@@ -207,8 +207,8 @@ void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
 // block per vertex row, rows staged in LDS; lds = bytes of the staged rows
 void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
 // colour by colour over contiguous vertex ranges; needs list16, k, Y = X or
-// absent, L <= 4096, Cx <= 8 * 256 * (16 / element size), 16-byte aligned
-// rows, and lds = 2 * Cx (rounded up to 16 bytes) * element size
+// absent, L <= 4096, Cx <= 8192, 16-byte aligned rows, and
+// lds = 2 * Cx (rounded up to 16 bytes) * element size
 void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s);
