@@ -1272,7 +1272,7 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const size_t tile_lds = 2 * (size_t)round_up(X->cols, Nv) * x.es;
   const bool aligned = x.b == 1 || (X->cols * x.es) % 16 == 0;
   const bool use_tile = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && (!Y || a.same_xy) &&
-                        aligned && P.root_L <= 16 * 256 && X->cols <= 8192 && tile_lds <= x.lds_max;
+                        aligned && P.root_L <= 16 * 256 && X->cols <= 8192 && tile_lds <= 64 * 1024;
   int nblk = 1024;
   if (use_tile)
     nblk = (int)std::min<int64_t>(kRootBlocks, (int64_t)x.cu_count *
