@@ -1,5 +1,6 @@
 // Kernels of the colour-coding dynamic programme (SubGraph2Vec, arXiv
 // 2009.11665) for gfx950.  Host-side launchers are at the end of the file.
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -464,7 +465,8 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
   const float *fa = SCALED ? a.fa + (int64_t)j * a.Ca : nullptr;
   const float *fb = SCALED ? a.fb + (int64_t)j * a.Cb : nullptr;
   bool ovf = false;
-  if (SCALED)
+  const bool track = SCALED && a.mx != nullptr;  // else measured afterwards
+  if (track)
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0.f;
   const int64_t ntiles = (a.n + R - 1) / R;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
           if constexpr (SCALED) m = fmaxf(m, (float)acc[r]);
         }
       }
-      if constexpr (SCALED) lmx[C] = fmaxf(lmx[C], m);
+      if (track) lmx[C] = fmaxf(lmx[C], m);
     }
   }
   if constexpr (is_u64<T>) {
@@ -553,7 +555,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
   if constexpr (SCALED) {
     __syncthreads();
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
-      if (lmx[c] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + c, __float_as_uint(lmx[c]));
+      if (track && lmx[c] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + c, __float_as_uint(lmx[c]));
       if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
     }
   }
@@ -696,7 +698,9 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   const float *fb = SCALED ? a.fb + (int64_t)j * a.Cb : nullptr;
   const int32_t *cnt = a.counts + (int64_t)j * a.k;
   bool ovf = false;
-  if (SCALED)
+  // column maxima (FP32S) unless the caller measures them afterwards (mx null)
+  const bool track = SCALED && a.mx != nullptr;
+  if (track)
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0;
   int64_t ntiles = 0;
   for (int c = 0; c < a.k; ++c) ntiles += (cnt[c] + R - 1) / R;
@@ -759,7 +763,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
           if constexpr (SCALED) m = fmaxf(m, (float)acc[r]);
         }
       }
-      if constexpr (SCALED) {
+      if (track) {
         // column C belongs to this thread in every tile
         const uint32_t code = m > 0.f ? (__float_as_uint(m) >> 23) + 1u : 0u;
         if (code > lmx[C]) lmx[C] = (uint8_t)code;
@@ -774,7 +778,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
       // a float with the same floor(log2): 2^(field - 127), or the smallest
       // subnormal for a subnormal maximum
-      const uint32_t code = lmx[c];
+      const uint32_t code = track ? lmx[c] : 0u;
       if (code) atomicMax(a.mx + (int64_t)j * a.Cs + c, code == 1u ? 1u : (code - 1u) << 23);
       if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
     }
@@ -799,7 +803,8 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
   const int rsub = cpad >= BLOCK ? 0 : threadIdx.x / cpad;
   const int c0 = cpad >= BLOCK ? threadIdx.x : threadIdx.x - rsub * cpad;
   const int cstep = cpad >= BLOCK ? BLOCK : cpad;
-  if (SCALED)
+  const bool track = SCALED && a.mx != nullptr;
+  if (track)
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0.f;
   __syncthreads();
   for (int64_t i0 = (int64_t)blockIdx.x * rpi; i0 < a.n; i0 += (int64_t)gridDim.x * rpi) {
@@ -828,7 +833,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
         const int C = C0 + u * cstep;
         if (C < a.Cs) {
           orow[C] = v[u];
-          if constexpr (SCALED) {
+          if (track) {
             if ((float)v[u] > 0.f) {
               // one row per iteration: column C belongs to this thread
               if (rpi == 1) lmx[C] = fmaxf(lmx[C], (float)v[u]);
@@ -842,7 +847,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
   if constexpr (SCALED) {
     __syncthreads();
     for (int cc = threadIdx.x; cc < a.Cs; cc += BLOCK) {
-      if (lmx[cc] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + cc, __float_as_uint(lmx[cc]));
+      if (track && lmx[cc] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + cc, __float_as_uint(lmx[cc]));
       if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + cc] = a.Eb[j];
     }
   }
@@ -1130,6 +1135,18 @@ __global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int 
   }
   out[j] = s;
   if (o) atomicOr(ovf, 1);
+}
+
+// Column maxima of an FP32S table (float bits, atomicMax), for producers too
+// wide to keep them in LDS.  Grid: (column vectors, row groups).
+__global__ void __launch_bounds__(BLOCK) k_colmax(const float *X, int64_t n, int64_t ld, int64_t cols,
+                                                   unsigned *mx) {
+  const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= cols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * n / gridDim.y, r1 = (int64_t)(blockIdx.y + 1) * n / gridDim.y;
+  float m = 0.f;
+  for (int64_t i = r0; i < r1; ++i) m = fmaxf(m, X[i * ld + c]);
+  if (m > 0.f) atomicMax(mx + c, __float_as_uint(m));
 }
 
 // ===========================================================================
@@ -1442,6 +1459,13 @@ int launch_ema_colour(int dtype, const EmaColourArgs &a, int R, dim3 grid, size_
   if (dtype == DT_F32) return ema_colour_t<float, true>(a, R, grid, lds, s);
   if (dtype == DT_F64) return ema_colour_t<double, false>(a, R, grid, lds, s);
   return ema_colour_t<uint64_t, false>(a, R, grid, lds, s);
+}
+
+void launch_colmax(const float *X, int64_t n, int64_t ld, int64_t cols, unsigned *mx, hipStream_t s) {
+  if (n == 0 || cols == 0) return;
+  const int64_t gx = (cols + BLOCK - 1) / BLOCK;
+  const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, (4096 + gx - 1) / gx));
+  k_colmax<<<dim3((unsigned)gx, (unsigned)gy), BLOCK, 0, s>>>(X, n, ld, cols, mx);
 }
 
 void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,

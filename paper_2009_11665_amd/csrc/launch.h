@@ -197,6 +197,9 @@ void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s);
 // unroll: gathers in flight per stream (4 or 8)
 int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipStream_t s);
 void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s);
+// mx[c] = max over rows of X(i, c) (float bits, atomicMax), c < cols; mx
+// must start at zero
+void launch_colmax(const float *X, int64_t n, int64_t ld, int64_t cols, unsigned *mx, hipStream_t s);
 void launch_xsplit_combine(int dtype, const XsplitCombineArgs &a, hipStream_t s);
 void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
                        int64_t n_tasks, int64_t n, int xs, uint16_t *out, hipStream_t s);

@@ -26,24 +26,33 @@ void set_error(const char *fmt, ...) {
 
 const char *last_error() { return g_err; }
 
-int64_t binom(int a, int b) {
-  static int64_t tab[65][65];
-  static std::once_flag once;
-  std::call_once(once, [] {
+namespace {
+// Pascal's triangle up to 64, filled when the library is loaded
+struct BinomTable {
+  int64_t t[65][65];
+  BinomTable() {
     for (int x = 0; x <= 64; ++x) {
-      tab[x][0] = 1;
-      for (int y = 1; y <= 64; ++y) tab[x][y] = (x == 0) ? 0 : tab[x - 1][y - 1] + tab[x - 1][y];
+      t[x][0] = 1;
+      for (int y = 1; y <= 64; ++y) t[x][y] = (x == 0) ? 0 : t[x - 1][y - 1] + t[x - 1][y];
     }
-  });
+  }
+};
+const BinomTable g_binom;
+}  // namespace
+
+int64_t binom(int a, int b) {
   if (a < 0 || b < 0 || a > 64 || b > 64) return 0;
-  return tab[a][b];
+  return g_binom.t[a][b];
 }
 
 int64_t colex_rank(uint32_t mask) {
   int64_t r = 0;
   int i = 0;
-  for (int c = 0; c < 32; ++c)
-    if (mask >> c & 1u) r += binom(c, ++i);
+  while (mask) {
+    const int c = __builtin_ctz(mask);
+    mask &= mask - 1;
+    r += g_binom.t[c][++i];
+  }
   return r;
 }
 
@@ -300,9 +309,12 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
   }
 
   // Colour-restricted tables of general splits (active child with more than
-  // one vertex), built when every compact position fits 16 bits.
-  for (auto &nd : P->nodes) {
-    if (nd.size == 1) continue;
+  // one vertex), built when every compact position fits 16 bits and the
+  // per-colour pair lists stay below 2^26 entries.  The root split is reduced
+  // from its children's tables (root lists below) and gets none.
+  for (size_t ni = 0; ni < P->nodes.size(); ++ni) {
+    Node &nd = P->nodes[ni];
+    if (nd.size == 1 || (int)ni == P->root) continue;
     const Node &A = P->nodes[nd.active];
     const Node &Pn = P->nodes[nd.passive];
     if (A.size == 1) continue;
@@ -312,7 +324,7 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
     nd.c_u = binom(k - 1, m - 1);
     nd.c_z = binom(k - 1, m);
     nd.c_q = (int)binom(m - 1, ma - 1);
-    if (nd.c_sa >= 0xFFFF || nd.c_sb >= 0xFFFF) {
+    if (nd.c_sa >= 0xFFFF || nd.c_sb >= 0xFFFF || (double)k * nd.c_q * nd.c_u > (double)(1 << 26)) {
       nd.c_q = 0;
       continue;
     }
@@ -322,37 +334,47 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
     nd.co.resize((size_t)k * nd.c_u);
     nd.cz.resize((size_t)k * nd.c_z);
     nd.cp.resize((size_t)k * nd.c_q * nd.c_u);
-    std::vector<int32_t> posa(ca_cols), posb(cb_cols);
+    // compact positions: posa[c][I_a] among active sets holding c, posb[c][I_p]
+    // among passive sets without c, and u[c][I_s] among output sets holding c
+    std::vector<int32_t> posa((size_t)k * ca_cols, -1), posb((size_t)k * cb_cols, -1);
+    std::vector<int32_t> ucol((size_t)k * nd.cols, -1);
     for (int c = 0; c < k; ++c) {
       int64_t na = 0, nb = 0, nu = 0, nz = 0;
-      for (int64_t r = 0; r < ca_cols; ++r) {
-        posa[r] = -1;
+      for (int64_t r = 0; r < ca_cols; ++r)
         if (colex_unrank(r, ma, k) >> c & 1u) {
-          posa[r] = (int32_t)na;
+          posa[(size_t)c * ca_cols + r] = (int32_t)na;
           nd.ca[(size_t)c * nd.c_sa + na++] = (int32_t)r;
         }
-      }
-      for (int64_t r = 0; r < cb_cols; ++r) {
-        posb[r] = -1;
+      for (int64_t r = 0; r < cb_cols; ++r)
         if (!(colex_unrank(r, mp, k) >> c & 1u)) {
-          posb[r] = (int32_t)nb;
+          posb[(size_t)c * cb_cols + r] = (int32_t)nb;
           nd.cb[(size_t)c * nd.c_sb + nb++] = (int32_t)r;
         }
-      }
       for (int64_t r = 0; r < nd.cols; ++r) {
-        if (!(colex_unrank(r, m, k) >> c & 1u)) {
+        if (colex_unrank(r, m, k) >> c & 1u) {
+          ucol[(size_t)c * nd.cols + r] = (int32_t)nu;
+          nd.co[(size_t)c * nd.c_u + nu++] = (int32_t)r;
+        } else {
           nd.cz[(size_t)c * nd.c_z + nz++] = (int32_t)r;
-          continue;
         }
-        const int64_t u = nu++;
-        nd.co[(size_t)c * nd.c_u + u] = (int32_t)r;
-        int q = 0;
-        for (int t = 0; t < nd.np; ++t) {
-          const int32_t ia = nd.pairs[((size_t)r * nd.np + t) * 2 + 0];
-          const int32_t ip = nd.pairs[((size_t)r * nd.np + t) * 2 + 1];
-          if (posa[ia] < 0) continue;  // active set without c: M_a(i, .) = 0
-          nd.cp[((size_t)c * nd.c_q + q) * nd.c_u + u] = (uint32_t)posa[ia] | ((uint32_t)posb[ip] << 16);
-          ++q;
+      }
+    }
+    // one walk over the pairs: a pair contributes to the colours of its
+    // active set (M_a(i, I_a) = 0 for a vertex whose colour is not in I_a)
+    std::vector<int32_t> qn(k);
+    for (int64_t r = 0; r < nd.cols; ++r) {
+      std::fill(qn.begin(), qn.end(), 0);
+      for (int t = 0; t < nd.np; ++t) {
+        const int32_t ia = nd.pairs[((size_t)r * nd.np + t) * 2 + 0];
+        const int32_t ip = nd.pairs[((size_t)r * nd.np + t) * 2 + 1];
+        uint32_t Am = colex_unrank(ia, ma, k);
+        while (Am) {
+          const int c = __builtin_ctz(Am);
+          Am &= Am - 1;
+          const int64_t u = ucol[(size_t)c * nd.cols + r];
+          nd.cp[((size_t)c * nd.c_q + qn[c]) * nd.c_u + u] =
+              (uint32_t)posa[(size_t)c * ca_cols + ia] | ((uint32_t)posb[(size_t)c * cb_cols + ip] << 16);
+          ++qn[c];
         }
       }
     }
@@ -385,11 +407,13 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
       P->root_kind = fuse ? ROOT_FUSED : ROOT_GENERAL;
       P->root_x_node = fuse ? A.passive : R.active;
       if (fuse) P->fused[R.active] = 1;
+      std::vector<uint32_t> amask(binom(k, A.size));
+      for (size_t x = 0; x < amask.size(); ++x) amask[x] = colex_unrank((int64_t)x, A.size, k);
       for (int64_t r = 0; r < nout; ++r) {
         for (int q = 0; q < R.np; ++q) {
           int32_t ia = R.pairs[((size_t)r * R.np + q) * 2 + 0];
           int32_t ip = R.pairs[((size_t)r * R.np + q) * 2 + 1];
-          uint32_t S = colex_unrank(ia, A.size, k);
+          uint32_t S = amask[ia];
           for (int c = 0; c < k; ++c)
             if (S >> c & 1u) {
               lists[c].push_back(fuse ? (int32_t)colex_rank(S & ~(1u << c)) : ia);

@@ -1057,7 +1057,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
 // fit: picks the rows per tile and the grid, then launches k_ema_general.
 sg2v_status launch_general(Ctx &x, EmaArgs &a) {
   const bool sc = x.dt == DT_F32;
-  const size_t lmx = sc ? (size_t)a.Cs * 4 : 0;
+  const size_t lmx = (sc && a.mx) ? (size_t)a.Cs * 4 : 0;
   sg2v_tuning_t tu = tuning();
   const size_t budget = std::min<size_t>(x.lds_max, 64 * 1024);
   const size_t rowb = (size_t)((a.Ca | 1) + (a.Cb | 1)) * x.es;
@@ -1081,8 +1081,9 @@ sg2v_status launch_general(Ctx &x, EmaArgs &a) {
 
 // Colour-restricted multiply-add of a general split: vertices are grouped by
 // colour once per pass, then k_ema_colour works on tiles of one colour.
-sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
+sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g, bool *done) {
   const Node &nd = x.P->nodes[node];
+  *done = false;
   const int k = x.P->k;
   int32_t *counts = (int32_t *)x.ws->bucket.p;
   int32_t *cursor = counts + (size_t)x.b * 32;
@@ -1126,7 +1127,7 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
   a.es = g.es;
   a.ovf = g.ovf;
   const bool sc = x.dt == DT_F32;
-  const size_t lmx = sc ? (size_t)round_up(nd.cols, 16) : 0;  // one byte per output column
+  const size_t lmx = (sc && g.mx) ? (size_t)round_up(nd.cols, 16) : 0;  // one byte per output column
   const size_t budget = std::min<size_t>(x.lds_max, 80 * 1024);
   // staged columns hold R rows plus one 16-byte vector of padding
   const int Nv = 16 / (int)x.es;
@@ -1138,10 +1139,7 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
   while (R > 4 && lds_for(R) > budget) R /= 2;
   if (R < 4) R = 4;
   const size_t lds = lds_for(R);
-  if (lds > x.lds_max) {
-    set_error("sg2v_count: colour-restricted eMA needs %zu bytes of LDS", lds);
-    return SG2V_ERANGE;
-  }
+  if (lds > x.lds_max) return SG2V_OK;  // staging does not fit: the general kernel runs
   const int64_t ntiles = x.g->n / R + k;
   const int64_t per_cu = std::max<int64_t>(1, (int64_t)(x.lds_max / lds));
   const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8));
@@ -1152,6 +1150,7 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g) {
     set_error("sg2v_count: no colour-restricted eMA variant for R=%d", R);
     return SG2V_EINVAL;
   }
+  *done = true;
   return SG2V_OK;
 }
 
@@ -1183,11 +1182,11 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
     a.es = Ms.e;
     launch_fill_u32(Ms.mx, Ms.cols * x.b, 0u, x.s);
   }
-  const size_t lmx = sc ? (size_t)nd.cols * 4 : 0;
-  if (lmx > x.lds_max) {
-    set_error("sg2v_count: table with %lld columns is too wide for FP32S", (long long)nd.cols);
-    return SG2V_ERANGE;
-  }
+  // FP32S tables too wide for per-block column maxima in LDS get them from a
+  // pass over the finished table instead
+  const bool wide = sc && (size_t)nd.cols * 4 > 32 * 1024;
+  if (wide) a.mx = nullptr;
+  const size_t lmx = (sc && !wide) ? (size_t)nd.cols * 4 : 0;
   if (single) {
     const int64_t cpad = round_up(nd.cols, 64);
     const int64_t rpi = cpad >= 256 ? 1 : 256 / cpad;
@@ -1205,15 +1204,17 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
       a.fa = Ma.f;
       a.Ea = Ma.E;
     }
-    if (nd.c_q > 0 && x.dp.cpr[node] && !(tuning().flags & SG2V_TUNE_NO_COLOR_EMA)) {
-      ST_TRY(ema_colour(x, node, a));
-    } else {
+    bool done = false;
+    if (nd.c_q > 0 && x.dp.cpr[node] && !(tuning().flags & SG2V_TUNE_NO_COLOR_EMA))
+      ST_TRY(ema_colour(x, node, a, &done));
+    if (!done) {
       ProfScope ps(SG2V_K_EMA_GENERAL,
                    (double)x.g->n * x.b * (double)(nd.cols + Ma.cols + Bt.cols) * x.es,
                    (double)x.g->n * x.b * (double)nd.cols * nd.np, x.s);
       ST_TRY(launch_general(x, a));
     }
   }
+  if (wide) launch_colmax((const float *)Ms.p, x.g->n, Ms.ld, Ms.cols * x.b, Ms.mx, x.s);
   if (x.dt == DT_U64) launch_zero_pad(x.dt, Ms.p, x.g->n, Ms.ld, Ms.cols * x.b, x.s);
   norm(x, Ms);
   return SG2V_OK;

@@ -334,3 +334,49 @@ def test_bintree15_u64_exact_both_root_paths(flags):
     say("bt15 u64", flags, ref, list(r["colorful_u64"]))
     assert [int(x) for x in r["colorful_u64"]] == ref
     np.testing.assert_allclose(r32["colorful"], ref64, rtol=FP32_TOL)
+
+
+def _complete_graph(n):
+    return gg.from_edge_list(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+
+
+def _colourful_in_complete(t, colours, k):
+    """Colourful maps of any t-vertex tree into K_n: every injective map is a
+    homomorphism, so the count is t! times the number of t-sets of vertices
+    with distinct colours, e_t(n_0, ..., n_{k-1}) (elementary symmetric
+    polynomial of the colour class sizes)."""
+    sizes = np.bincount(colours, minlength=k)
+    e = [1] + [0] * t
+    for s in sizes:
+        for q in range(t, 0, -1):
+            e[q] += e[q - 1] * int(s)
+    return math.factorial(t) * e[t]
+
+
+@pytest.mark.parametrize("par,k", [
+    (list(range(-1, 19)), 20),                 # 20-vertex path, the largest template
+    (gg.BINTREE15, 17),
+    ([-1, 0, 0, 0, 1, 1, 2, 2, 3, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13], 20),
+    (gg.CATERPILLAR10, 17),
+    (gg.PATH8, 8),
+])
+def test_large_k_on_complete_graph(par, k):
+    """k up to 20 (tables of C(20, 10) columns, splits beyond the 16-bit
+    colour-restricted tables) on K_40 against the closed form t! e_t(n_c):
+    exact mod 2^64, FP64 and FP32 within their tolerances."""
+    G = _complete_graph(40)
+    g = sg.Graph.from_csr(G)
+    t = len(par)
+    c = sg.Colorings(g, k, 31, 2)
+    cols = c.download()
+    p = sg.Plan(par, k)
+    ru = sg.count(p, g, c, "u64")
+    r64 = sg.count(p, g, c, "fp64")
+    r32 = sg.count(p, g, c, "fp32s")
+    for j in range(2):
+        exact = _colourful_in_complete(t, cols[j], k)
+        say("complete", t, k, j, exact)
+        np.testing.assert_array_equal(cols[j], O.colors(G.n, k, 31, j))
+        assert int(ru["colorful_u64"][j]) == exact % (1 << 64)
+        assert r64["colorful"][j] == pytest.approx(float(exact), rel=FP64_TOL)
+        assert r32["colorful"][j] == pytest.approx(float(exact), rel=FP32_TOL)
