@@ -136,6 +136,48 @@ def write_traffic(spmm_fetch, spmm_write, copy_fetch, copy_write, copy_mib):
     print(json.dumps(out))
 
 
+def batch_workload(sg, gg, torch, reps=3):
+    """Three templates of uneven size (bintree7, path8, caterpillar10, k = t)
+    x 16 colourings on Chung-Lu n = 500,000, mean degree 20: all passes of all
+    templates recorded as one HIP graph (sg2v_count_batch, replayed), against
+    the same counts run template by template, colouring included.  Tuning
+    from the autotuner on the widest template."""
+    G = gg.chung_lu_500k()
+    g = sg.Graph.from_csr(G)
+    pars = (gg.BINTREE7, gg.PATH8, gg.CATERPILLAR10)
+    plans = [sg.Plan(p) for p in pars]
+    ncol, seed = 16, 4
+    old = sg.get_tuning()
+    try:
+        tuned = sg.autotune(plans[2], g, "fp32s", 2)
+        sg.count_batch(plans, g, seed, ncol, "fp32s")  # records and caches the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            cf, _ = sg.count_batch(plans, g, seed, ncol, "fp32s")
+        torch.cuda.synchronize()
+        t_graph = (time.perf_counter() - t0) / reps
+        for p, par in zip(plans, pars):  # warm
+            sg.count(p, g, sg.Colorings(g, len(par), seed, ncol), "fp32s")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for p, par in zip(plans, pars):
+                sg.count(p, g, sg.Colorings(g, len(par), seed, ncol), "fp32s")
+        torch.cuda.synchronize()
+        t_seq = (time.perf_counter() - t0) / reps
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+    return {
+        "workload": "chung-lu n=500000 d=20 gamma=2.1; bintree7, path8, caterpillar10 (k=t) x 16 colourings, fp32s",
+        "template_colorings_per_s": 3 * ncol / t_graph,
+        "ms_one_graph_launch": t_graph * 1e3,
+        "ms_template_by_template": t_seq * 1e3,
+        "tuning": {"spmm_width": tuned.spmm_width, "ema_rows": tuned.ema_rows, "batch": tuned.batch,
+                   "flags": tuned.flags},
+    }
+
+
 def cpu_baseline(parent, k, scale, seed, full_n, full_nnz):
     """The oracle (FP64, OpenMP over vertices) on a bounded sample: the same
     template and colouring rule on an RMAT graph of 2^scale vertices with the
@@ -176,6 +218,8 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=14)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch-workload", action="store_true",
+                    help="skip the multi-template batch measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -318,7 +362,11 @@ def main():
             "gather_model_GBps": (sp["work"] * 4 / (sp["ms"] * 1e-3) / 1e9) if sp["ms"] else None,
         },
         "cpu_baseline": None,
+        "batch_workload": None,
     }
+    if not args.no_batch_workload:
+        log("batch workload (3 templates x 16 colourings) ...")
+        out["batch_workload"] = batch_workload(sg, gg, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(parent, k, args.cpu_scale, args.seed, G.n, G.nnz)
