@@ -239,15 +239,19 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
  * (vertices grouped by colour); budget_bytes: device memory the count may use. */
 #define SG2V_TUNE_NO_COLOR_SKIP 1
 #define SG2V_TUNE_NO_COLOR_EMA 2
-#define SG2V_TUNE_SPMM_UNROLL4 4 /* 4 row gathers in flight per SpMM stream instead of 8 */
+#define SG2V_TUNE_SPMM_UNROLL4 4 /* 4 row gathers in flight per SpMM stream (default below a mean
+                                    degree of 64) */
+#define SG2V_TUNE_SPMM_UNROLL8 128 /* 8 row gathers in flight per SpMM stream (default from a mean
+                                      degree of 64) */
 #define SG2V_TUNE_NO_XSPLIT 8    /* never split long SpMM tasks over the XCDs, and keep 128-byte
                                     chunks (overrides the two below) */
 #define SG2V_TUNE_FORCE_XSPLIT 16 /* split even when a chunk fits the caches (tests) */
 #define SG2V_TUNE_XSPLIT 32      /* split long SpMM tasks over the XCDs' neighbour ranges when one
                                     column chunk of the gathered table exceeds 32 MB, also with an
                                     explicit spmm_width (with spmm_width 0 this is automatic on
-                                    graphs of at least 262,144 vertices, which also get 256-byte
-                                    chunks) */
+                                    graphs of at least 262,144 vertices whose tasks of 512 or more
+                                    neighbours hold at least half the entries; such graphs also
+                                    get 256-byte chunks in any case) */
 #define SG2V_TUNE_ROOT_ROWS 64   /* root reduction one vertex per block step in vertex order instead
                                     of colour by colour with double-buffered rows */
 typedef struct {

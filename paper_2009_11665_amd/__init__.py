@@ -319,6 +319,7 @@ def count_grad(plan: Plan, graph: Graph, col: Colorings, grad_colorful, mode="fp
 TUNE_NO_COLOR_SKIP = 1
 TUNE_NO_COLOR_EMA = 2
 TUNE_SPMM_UNROLL4 = 4
+TUNE_SPMM_UNROLL8 = 128
 TUNE_NO_XSPLIT = 8
 TUNE_FORCE_XSPLIT = 16
 TUNE_XSPLIT = 32

@@ -1120,6 +1120,68 @@ __global__ void __launch_bounds__(BLOCK) k_root_tile(RootArgs a) {
   }
 }
 
+// Root reduction for narrow tables and short lists: one thread per vertex
+// (grid stride), every colour's (x, y) list staged in LDS, row entries read
+// directly (they share a few cache lines).  Each thread accumulates its
+// vertices in double (uint64 in U64); fixed-order block reduction.
+template <typename T, bool SCALED, bool HASY>
+__global__ void __launch_bounds__(BLOCK) k_root_thread(RootArgs a) {
+  using A = Arith<T>;
+  using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Acc red[WAVES_PER_BLOCK];
+  uint32_t *lists = (uint32_t *)smem;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int j = blockIdx.y;
+  for (int64_t q = threadIdx.x; q < (int64_t)a.k * a.L; q += BLOCK) lists[q] = a.list16[q];
+  __syncthreads();
+  const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
+  const T *X = (const T *)a.X;
+  const T *Y = (const T *)a.Y;
+  const float *fx = SCALED ? a.fx + (int64_t)j * a.Cx : nullptr;
+  const float *fy = (SCALED && HASY) ? a.fy + (int64_t)j * a.Cy : nullptr;
+  bool ovf = false;
+  Acc tot = Acc(0);
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * BLOCK) {
+    const uint32_t *lc = lists + (int64_t)col[i] * a.L;
+    const T *xr = X + i * a.ldx + (int64_t)j * a.Cx;
+    const T *yr = HASY ? Y + i * a.ldy + (int64_t)j * a.Cy : nullptr;
+    T s = T(0);
+    for (int q = 0; q < a.L; ++q) {
+      const uint32_t p = lc[q];
+      T x = xr[p & 0xFFFFu];
+      if constexpr (SCALED) x *= fx[p & 0xFFFFu];
+      if constexpr (HASY) {
+        T y = yr[p >> 16];
+        if constexpr (SCALED) y *= fy[p >> 16];
+        s = A::fma(x, y, s, ovf);
+      } else {
+        s = A::add(s, x, ovf);
+      }
+    }
+    if constexpr (is_u64<Acc>) tot = A::add(tot, s, ovf);
+    else tot += (double)s;
+  }
+  for (int off = 1; off < WAVE; off <<= 1) {
+    if constexpr (is_u64<Acc>) tot = A::add(tot, shfl_xor(tot, off), ovf);
+    else tot += shfl_xor(tot, off);
+  }
+  if (lane == 0) red[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Acc b = red[0];
+    for (int q = 1; q < WAVES_PER_BLOCK; ++q) {
+      if constexpr (is_u64<Acc>) b = A::add(b, red[q], ovf);
+      else b += red[q];
+    }
+    ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = b;
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+}
+
 template <typename Acc>
 __global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1392,6 +1454,19 @@ static void root_lds_t(const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) 
   auto kern = a.Y ? k1 : k0;
   if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   kern<<<grid, BLOCK, lds, s>>>(a);
+}
+
+template <typename T, bool SC>
+static void root_thread_t(const RootArgs &a, dim3 grid, hipStream_t s) {
+  const size_t lds = (size_t)a.k * a.L * 4;
+  if (a.Y) k_root_thread<T, SC, true><<<grid, BLOCK, lds, s>>>(a);
+  else k_root_thread<T, SC, false><<<grid, BLOCK, lds, s>>>(a);
+}
+
+void launch_root_thread(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) {
+  if (dtype == DT_F32) root_thread_t<float, true>(a, grid, s);
+  else if (dtype == DT_F64) root_thread_t<double, false>(a, grid, s);
+  else root_thread_t<uint64_t, false>(a, grid, s);
 }
 
 template <typename T, bool SC>

@@ -213,6 +213,8 @@ void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStr
 // absent, L <= 4096, Cx <= 8192, 16-byte aligned rows, and
 // lds = 2 * Cx (rounded up to 16 bytes) * element size
 void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
+// one thread per vertex; needs list16, k * L <= 8192 (lists staged in LDS)
+void launch_root_thread(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s);
 void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,

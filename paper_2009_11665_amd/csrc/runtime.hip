@@ -187,6 +187,7 @@ struct sg2v_graph {
   int64_t *task_beg = nullptr;
   int64_t n_tasks = 0, n_slots = 0;
   std::vector<int32_t> h_task_len;  // sorted lengths
+  double long_share = 0.0;          // share of the entries in tasks of >= kXsplitMin neighbours
   int32_t *long_row = nullptr, *long_slot0 = nullptr, *long_nslot = nullptr;
   int32_t n_long = 0;
   std::map<int, UnitTable> units;  // by G (lanes per neighbour row segment)
@@ -303,6 +304,14 @@ sg2v_status graph_tasks(sg2v_graph *g, const std::vector<int64_t> &rp, hipStream
   g->n_tasks = T;
   g->n_slots = slots;
   g->h_task_len = slen;
+  {
+    int64_t in_long = 0, all = 0;
+    for (int64_t x = 0; x < T; ++x) {
+      all += slen[x];
+      if (slen[x] >= kXsplitMin) in_long += slen[x];
+    }
+    g->long_share = all > 0 ? (double)in_long / (double)all : 0.0;
+  }
   void *p;
   ST_TRY(upload(srow, &p, s)); g->task_row = (int32_t *)p; g->allocs.push_back(p);
   ST_TRY(upload(slen, &p, s)); g->task_len = (int32_t *)p; g->allocs.push_back(p);
@@ -901,7 +910,9 @@ sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t 
   const sg2v_tuning_t tu = tuning();
   const int fl = tu.flags;
   if ((fl & SG2V_TUNE_NO_XSPLIT) || U->x_units == 0) return SG2V_OK;
-  const bool wanted = (fl & SG2V_TUNE_XSPLIT) || (tu.spmm_width == 0 && large_graph(x.g->n));
+  // automatic: large graphs whose long tasks hold at least half the entries
+  const bool wanted = (fl & SG2V_TUNE_XSPLIT) ||
+                      (tu.spmm_width == 0 && large_graph(x.g->n) && x.g->long_share >= 0.5);
   if (!(fl & SG2V_TUNE_FORCE_XSPLIT) && (!wanted || (double)x.g->n * W * x.es < 32.0 * (1 << 20)))
     return SG2V_OK;
   sg2v_graph *g = x.g;
@@ -964,7 +975,13 @@ sg2v_status step_spmm(Ctx &x, int node) {
   }
   if (x.dt == DT_F32) launch_fill_u32(B.mx, nc, 0u, x.s);
   const int64_t chunks = (nc + W - 1) / W;
-  const int unroll = (tuning().flags & SG2V_TUNE_SPMM_UNROLL4) ? 4 : 8;
+  // gathers in flight per stream: 8 for long neighbour lists (mean degree
+  // >= 64), else 4 (fewer registers, more waves)
+  const int fl = tuning().flags;
+  const int unroll = (fl & SG2V_TUNE_SPMM_UNROLL4)   ? 4
+                     : (fl & SG2V_TUNE_SPMM_UNROLL8) ? 8
+                     : (x.g->nnz >= 64 * x.g->n)     ? 8
+                                                     : 4;
   a.chunk0 = 0;
   a.xsplit = 0;
   a.xunits = 0;
@@ -1274,15 +1291,21 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const bool aligned = x.b == 1 || (X->cols * x.es) % 16 == 0;
   const bool use_tile = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && (!Y || a.same_xy) &&
                         aligned && P.root_L <= 16 * 256 && X->cols <= 8192 && tile_lds <= 64 * 1024;
+  // narrow rows and short lists: one thread per vertex
+  const bool use_thread = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && P.root_L <= 256 &&
+                          (int64_t)P.k * P.root_L <= 8192 && X->cols <= 512 && (!Y || Y->cols <= 512);
   int nblk = 1024;
-  if (use_tile)
+  if (use_thread)
+    nblk = (int)std::min<int64_t>(kRootBlocks, std::max<int64_t>(1, (x.g->n + 255) / 256));
+  else if (use_tile)
     nblk = (int)std::min<int64_t>(kRootBlocks, (int64_t)x.cu_count *
                                                    std::max<int64_t>(1, (int64_t)(x.lds_max / tile_lds)));
   {
     ProfScope ps(SG2V_K_ROOT,
                  (double)x.g->n * x.b * (double)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es,
                  (double)x.g->n * x.b * (double)P.root_L, x.s);
-    if (use_tile) launch_root_tile(x.dt, a, dim3(nblk, x.b), tile_lds, x.s);
+    if (use_thread) launch_root_thread(x.dt, a, dim3(nblk, x.b), x.s);
+    else if (use_tile) launch_root_tile(x.dt, a, dim3(nblk, x.b), tile_lds, x.s);
     else if (use_lds) launch_root_lds(x.dt, a, dim3(nblk, x.b), stage, x.s);
     else launch_root(x.dt, a, dim3(nblk, x.b), x.s);
   }
@@ -2143,9 +2166,10 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
   std::vector<sg2v_tuning_t> cand;
   const int widths[] = {16, 32, 64};
   const int rows[] = {4, 8, 16};
-  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_XSPLIT;
+  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_SPMM_UNROLL8 | SG2V_TUNE_XSPLIT;
   for (int w : widths)
-    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL4, (int)SG2V_TUNE_XSPLIT}) {
+    for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL4, (int)SG2V_TUNE_SPMM_UNROLL8,
+                   (int)SG2V_TUNE_XSPLIT}) {
       sg2v_tuning_t t = base;
       t.spmm_width = w;
       t.flags = (base.flags & ~skipfl) | fl;

@@ -211,7 +211,8 @@ def test_spmm_widths_agree(small_rmat):
             for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA, sg.TUNE_SPMM_UNROLL4,
                        sg.TUNE_FORCE_XSPLIT, sg.TUNE_FORCE_XSPLIT | sg.TUNE_NO_COLOR_SKIP,
                        sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA | sg.TUNE_SPMM_UNROLL4,
-                       sg.TUNE_XSPLIT, sg.TUNE_ROOT_ROWS):
+                       sg.TUNE_XSPLIT, sg.TUNE_ROOT_ROWS, sg.TUNE_SPMM_UNROLL8,
+                       sg.TUNE_SPMM_UNROLL8 | sg.TUNE_FORCE_XSPLIT):
                 sg.set_tuning(spmm_width=w, flags=fl)
                 say("spmm width", w, "flags", fl)
                 got = sg.count(p, g, c, "u64")["colorful_u64"]
