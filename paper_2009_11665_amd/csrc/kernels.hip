@@ -787,68 +787,66 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
 
 // Count combination when the active child is one vertex (Alg. 2's
 // single-vertex table): M_s(i, C) = [col(i) in C] * B(i, C \ {col(i)}).
-// Threads own output columns; a block handles `rows_per_iter` rows at once.
-
+// A block takes tiles of rows with all nb colourings of the pass, threads
+// over (row, colouring, column) in row-major order so that the writes are
+// contiguous; eight elements' loads (colour, drop index, B entry) are in
+// flight per thread.  Also the adjoint's B-bar(i, P) = M-bar(i, P + col(i))
+// (drop = the plan's add table).
 template <typename T, bool SCALED>
 __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
+  constexpr int U = 8;
   extern __shared__ __align__(16) unsigned char smem[];
-  float *lmx = (float *)smem;
-  const int j = blockIdx.y;
-  const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
+  unsigned *lmx = (unsigned *)smem;  // [nb * Cs] column maxima (FP32S)
+  const bool track = SCALED && a.mx != nullptr;
+  const int W = a.Cs * a.nb;  // output entries per row
+  const int R = max(1, (4 * U * BLOCK) / W);  // rows per tile: about four rounds of loads
   const T *Bt = (const T *)a.B;
   T *Ms = (T *)a.Ms;
-  const float *fb = SCALED ? a.fb + (int64_t)j * a.Cb : nullptr;
-  const int cpad = (a.Cs + WAVE - 1) / WAVE * WAVE;
-  const int rpi = cpad >= BLOCK ? 1 : BLOCK / cpad;  // rows per iteration
-  const int rsub = cpad >= BLOCK ? 0 : threadIdx.x / cpad;
-  const int c0 = cpad >= BLOCK ? threadIdx.x : threadIdx.x - rsub * cpad;
-  const int cstep = cpad >= BLOCK ? BLOCK : cpad;
-  const bool track = SCALED && a.mx != nullptr;
   if (track)
-    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0.f;
+    for (int c = threadIdx.x; c < W; c += BLOCK) lmx[c] = 0u;
   __syncthreads();
-  for (int64_t i0 = (int64_t)blockIdx.x * rpi; i0 < a.n; i0 += (int64_t)gridDim.x * rpi) {
-    const int64_t i = i0 + rsub;
-    if (rsub >= rpi || i >= a.n) continue;
-    const int c = col[i];
-    const T *__restrict__ brow = Bt + i * a.ldb + (int64_t)j * a.Cb;
-    T *__restrict__ orow = Ms + i * a.lds + (int64_t)j * a.Cs;
-    const int32_t *__restrict__ drop = a.drop + (int64_t)c * a.Cs;
-    // eight columns in flight per thread
-    constexpr int U = 8;
-    for (int C0 = c0; C0 < a.Cs; C0 += U * cstep) {
-      T v[U];
+  for (int64_t i0 = (int64_t)blockIdx.x * R; i0 < a.n; i0 += (int64_t)gridDim.x * R) {
+    const int E = (int)min<int64_t>(R, a.n - i0) * W;  // below 2^31: R * W <= 4 * U * BLOCK + W
+    for (int e0 = threadIdx.x; e0 < E; e0 += U * BLOCK) {
+      int64_t row[U];
+      int jj[U], cl[U], cc[U], c[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int C = C0 + u * cstep;
-        const int idx = C < a.Cs ? drop[C] : -1;
-        v[u] = T(0);
-        if (idx >= 0) {
-          v[u] = brow[idx];
-          if constexpr (SCALED) v[u] *= fb[idx];
-        }
+        const int e = min(e0 + u * BLOCK, E - 1);
+        const int r = e / W;
+        cc[u] = e - r * W;
+        jj[u] = cc[u] / a.Cs;
+        cl[u] = cc[u] - jj[u] * a.Cs;
+        row[u] = i0 + r;
+        c[u] = a.colors[(int64_t)(a.j0 + jj[u]) * a.n + row[u]];
+      }
+      int idx[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) idx[u] = a.drop[(int64_t)c[u] * a.Cs + cl[u]];
+      T v[U];
+      float f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t src = (int64_t)jj[u] * a.Cb + max(idx[u], 0);
+        v[u] = Bt[row[u] * a.ldb + src];
+        f[u] = SCALED ? a.fb[src] : 1.0f;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int C = C0 + u * cstep;
-        if (C < a.Cs) {
-          orow[C] = v[u];
-          if (track) {
-            if ((float)v[u] > 0.f) {
-              // one row per iteration: column C belongs to this thread
-              if (rpi == 1) lmx[C] = fmaxf(lmx[C], (float)v[u]);
-              else atomicMax((unsigned *)&lmx[C], __float_as_uint((float)v[u]));
-            }
-          }
+        if (e0 + u * BLOCK < E) {
+          T w = idx[u] >= 0 ? v[u] : T(0);
+          if constexpr (SCALED) w *= f[u];
+          Ms[row[u] * a.lds + cc[u]] = w;
+          if (track && (float)w > 0.f) atomicMax(&lmx[cc[u]], __float_as_uint((float)w));
         }
       }
     }
   }
   if constexpr (SCALED) {
     __syncthreads();
-    for (int cc = threadIdx.x; cc < a.Cs; cc += BLOCK) {
-      if (track && lmx[cc] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + cc, __float_as_uint(lmx[cc]));
-      if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + cc] = a.Eb[j];
+    for (int c = threadIdx.x; c < W; c += BLOCK) {
+      if (track && lmx[c]) atomicMax(a.mx + c, lmx[c]);
+      if (blockIdx.x == 0) a.es[c] = a.Eb[c / a.Cs];
     }
   }
 }

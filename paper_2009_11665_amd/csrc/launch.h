@@ -121,6 +121,7 @@ struct EmaArgs {
   int *es;               // FP32S output column exponents
   int *ovf;
   int32_t accumulate;    // general kernel: 1 adds into Ms (adjoint)
+  int32_t nb;            // single-vertex kernel: colourings in the pass (columns j * Cs + C)
 };
 
 // colour-restricted multiply-add (rows bucketed by colour)
@@ -205,6 +206,8 @@ void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const in
                        int64_t n_tasks, int64_t n, int xs, uint16_t *out, hipStream_t s);
 int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
                        hipStream_t s);
+// grid.y must be 1 (the kernel covers a.nb colourings); lds = nb * Cs * 4
+// when FP32S column maxima are tracked (a.mx non-null), else 0
 void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s);
 void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
 // block per vertex row, rows staged in LDS; lds = bytes of the staged rows

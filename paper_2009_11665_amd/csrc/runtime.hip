@@ -1201,14 +1201,16 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
   }
   // FP32S tables too wide for per-block column maxima in LDS get them from a
   // pass over the finished table instead
-  const bool wide = sc && (size_t)nd.cols * 4 > 32 * 1024;
+  // (the single-vertex kernel keeps all b colourings of the pass in a block)
+  const size_t lmx_cols = (size_t)nd.cols * (single ? x.b : 1);
+  const bool wide = sc && lmx_cols * 4 > (single ? 48 : 32) * 1024;
   if (wide) a.mx = nullptr;
-  const size_t lmx = (sc && !wide) ? (size_t)nd.cols * 4 : 0;
+  const size_t lmx = (sc && !wide) ? lmx_cols * 4 : 0;
   if (single) {
-    const int64_t cpad = round_up(nd.cols, 64);
-    const int64_t rpi = cpad >= 256 ? 1 : 256 / cpad;
-    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((x.g->n + rpi - 1) / rpi, 4096)),
-              (unsigned)x.b);
+    a.nb = x.b;
+    const int64_t rows = std::max<int64_t>(1, 8192 / ((int64_t)nd.cols * x.b));
+    const int64_t tiles = (x.g->n + rows - 1) / rows;
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)x.cu_count * 8)), 1);
     ProfScope ps(SG2V_K_EMA_SINGLE, (double)x.g->n * x.b * (double)(nd.cols + Bt.cols) * x.es,
                  (double)x.g->n * x.b * (double)nd.cols, x.s);
     launch_ema_single(x.dt, a, grid, lmx, x.s);
@@ -1909,9 +1911,9 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
           a.ldb = ld[q];
           a.Cb = (int32_t)cs;
           a.drop = x.dp.add[q];
-          const int64_t cpad = round_up(cp, 64);
-          const int64_t rpi = cpad >= 256 ? 1 : 256 / cpad;
-          dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((g->n + rpi - 1) / rpi, 4096)), 1);
+          a.nb = 1;
+          const int64_t rows = std::max<int64_t>(1, 8192 / cp);
+          dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((g->n + rows - 1) / rows, 2048)), 1);
           ProfScope ps(SG2V_K_EMA_SINGLE, (double)g->n * (cs + cp) * 8, (double)g->n * cp, s);
           launch_ema_single(DT_F64, a, grid, 0, s);
         }
