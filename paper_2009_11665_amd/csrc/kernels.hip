@@ -998,7 +998,7 @@ __global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
 // its share of every vertex's terms (summed per vertex in T) in double
 // (uint64 in U64); the block then reduces its threads in a fixed order.
 // Needs Cx <= PV * N * BLOCK, L <= LPT * BLOCK and 16-byte aligned rows.
-template <typename T, bool SCALED, bool HASY, int LPT, int PV>
+template <typename T, bool SCALED, bool HASY, int LPT, int PV, bool DB>
 __global__ void __launch_bounds__(BLOCK) k_root_tile(RootArgs a) {
   using A = Arith<T>;
   using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
@@ -1009,7 +1009,7 @@ __global__ void __launch_bounds__(BLOCK) k_root_tile(RootArgs a) {
   __shared__ Acc red[WAVES_PER_BLOCK];
   const int nvec = (a.Cx + N - 1) / N;
   T *lx0 = (T *)smem;
-  T *lx1 = lx0 + (int64_t)nvec * N;
+  T *lx1 = DB ? lx0 + (int64_t)nvec * N : lx0;  // single buffer: fetch after the sum
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   const int j = blockIdx.y;
@@ -1083,7 +1083,7 @@ __global__ void __launch_bounds__(BLOCK) k_root_tile(RootArgs a) {
         T *lx = (t & 1) ? lx1 : lx0;
         store(lx);
         __syncthreads();
-        if (t + 1 < cnt) fetch(rowlist[t + 1]);  // in flight during the sum
+        if (DB && t + 1 < cnt) fetch(rowlist[t + 1]);  // in flight during the sum
         T s = T(0);
 #pragma unroll
         for (int u = 0; u < LPT; ++u) {
@@ -1094,6 +1094,10 @@ __global__ void __launch_bounds__(BLOCK) k_root_tile(RootArgs a) {
         }
         if constexpr (is_u64<Acc>) tot = A::add(tot, s, ovf);
         else tot += (double)s;
+        if (!DB) {
+          __syncthreads();  // the buffer is free for the next row
+          if (t + 1 < cnt) fetch(rowlist[t + 1]);
+        }
       }
     }
   }
@@ -1468,20 +1472,19 @@ void launch_root_thread(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) 
 }
 
 template <typename T, bool SC>
-static void root_tile_t(const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+static void root_tile_t(const RootArgs &a, dim3 grid, size_t lds, bool db, hipStream_t s) {
   // 16-byte vectors per thread: rows of up to 8192 elements
   constexpr int PV = sizeof(T) == 4 ? 8 : 16;
-  auto k1 = k_root_tile<T, SC, true, 16, PV>;
-  auto k0 = k_root_tile<T, SC, false, 16, PV>;
-  auto kern = a.Y ? k1 : k0;
+  auto kern = a.Y ? (db ? k_root_tile<T, SC, true, 16, PV, true> : k_root_tile<T, SC, true, 16, PV, false>)
+                  : (db ? k_root_tile<T, SC, false, 16, PV, true> : k_root_tile<T, SC, false, 16, PV, false>);
   if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   kern<<<grid, BLOCK, lds, s>>>(a);
 }
 
-void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-  if (dtype == DT_F32) root_tile_t<float, true>(a, grid, lds, s);
-  else if (dtype == DT_F64) root_tile_t<double, false>(a, grid, lds, s);
-  else root_tile_t<uint64_t, false>(a, grid, lds, s);
+void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, bool db, hipStream_t s) {
+  if (dtype == DT_F32) root_tile_t<float, true>(a, grid, lds, db, s);
+  else if (dtype == DT_F64) root_tile_t<double, false>(a, grid, lds, db, s);
+  else root_tile_t<uint64_t, false>(a, grid, lds, db, s);
 }
 
 void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {

@@ -213,9 +213,9 @@ void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
 // block per vertex row, rows staged in LDS; lds = bytes of the staged rows
 void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
 // colour by colour over contiguous vertex ranges; needs list16, k, Y = X or
-// absent, L <= 4096, Cx <= 8192, 16-byte aligned rows, and
-// lds = 2 * Cx (rounded up to 16 bytes) * element size
-void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s);
+// absent, L <= 4096, Cx <= 8192, 16-byte aligned rows, and lds = (db ? 2 : 1)
+// * Cx (rounded up to 16 bytes) * element size (db: double-buffered rows)
+void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, bool db, hipStream_t s);
 // one thread per vertex; needs list16, k * L <= 8192 (lists staged in LDS)
 void launch_root_thread(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,

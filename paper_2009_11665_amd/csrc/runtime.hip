@@ -1289,7 +1289,9 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const bool use_lds = a.list16 && stage <= std::min<size_t>(x.lds_max, 64 * 1024);
   // colour by colour, double-buffered rows, lists in registers
   const int64_t Nv = 16 / x.es;
-  const size_t tile_lds = 2 * (size_t)round_up(X->cols, Nv) * x.es;
+  const size_t row_lds = (size_t)round_up(X->cols, Nv) * x.es;
+  const bool tile_db = 2 * row_lds <= 64 * 1024;  // else one row buffer
+  const size_t tile_lds = (tile_db ? 2 : 1) * row_lds;
   const bool aligned = x.b == 1 || (X->cols * x.es) % 16 == 0;
   const bool use_tile = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && (!Y || a.same_xy) &&
                         aligned && P.root_L <= 16 * 256 && X->cols <= 8192 && tile_lds <= 64 * 1024;
@@ -1307,7 +1309,7 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
                  (double)x.g->n * x.b * (double)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es,
                  (double)x.g->n * x.b * (double)P.root_L, x.s);
     if (use_thread) launch_root_thread(x.dt, a, dim3(nblk, x.b), x.s);
-    else if (use_tile) launch_root_tile(x.dt, a, dim3(nblk, x.b), tile_lds, x.s);
+    else if (use_tile) launch_root_tile(x.dt, a, dim3(nblk, x.b), tile_lds, tile_db, x.s);
     else if (use_lds) launch_root_lds(x.dt, a, dim3(nblk, x.b), stage, x.s);
     else launch_root(x.dt, a, dim3(nblk, x.b), x.s);
   }
