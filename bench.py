@@ -178,6 +178,32 @@ def batch_workload(sg, gg, torch, reps=3):
     }
 
 
+def adjoint_workload(sg, gg, torch, reps=2):
+    """The differentiation workload: Chung-Lu n = 262,144, mean degree 16,
+    gamma 2.1, edge weights U[0.5, 1.5); caterpillar10, k = 10; one colouring:
+    weighted FP64 count and its adjoint (d count / d w_e for every CSR entry,
+    sub-template tables recomputed)."""
+    G = gg.chung_lu_262k_weighted()
+    g = sg.Graph.from_csr(G)
+    p = sg.Plan(gg.CATERPILLAR10, 10)
+    c = sg.Colorings(g, 10, 3, 1)
+    sg.count(p, g, c, "fp64")
+    sg.count_grad(p, g, c, [1.0], "fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sg.count(p, g, c, "fp64")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        sg.count_grad(p, g, c, [1.0], "fp64")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": "chung-lu n=262144 d=16 gamma=2.1 weighted; caterpillar10 k=10; 1 colouring, fp64",
+            "ms_forward": (t1 - t0) / reps * 1e3, "ms_adjoint": (t2 - t1) / reps * 1e3,
+            "entries": G.nnz}
+
+
 def cpu_baseline(parent, k, scale, seed, full_n, full_nnz):
     """The oracle (FP64, OpenMP over vertices) on a bounded sample: the same
     template and colouring rule on an RMAT graph of 2^scale vertices with the
@@ -219,7 +245,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch-workload", action="store_true",
-                    help="skip the multi-template batch measurement")
+                    help="skip the multi-template batch and adjoint measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -363,10 +389,13 @@ def main():
         },
         "cpu_baseline": None,
         "batch_workload": None,
+        "adjoint_workload": None,
     }
     if not args.no_batch_workload:
         log("batch workload (3 templates x 16 colourings) ...")
         out["batch_workload"] = batch_workload(sg, gg, torch)
+        log("adjoint workload ...")
+        out["adjoint_workload"] = adjoint_workload(sg, gg, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(parent, k, args.cpu_scale, args.seed, G.n, G.nnz)
