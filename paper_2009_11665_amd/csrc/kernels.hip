@@ -1495,10 +1495,12 @@ void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStr
 
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s) {
+  // one thread per colouring of the pass
+  const unsigned blocks = (unsigned)((b + 63) / 64);
   if (dtype == DT_U64)
-    k_root_final<uint64_t><<<1, 64, 0, s>>>((const uint64_t *)partial, nblk, b, (uint64_t *)out, ovf);
+    k_root_final<uint64_t><<<blocks, 64, 0, s>>>((const uint64_t *)partial, nblk, b, (uint64_t *)out, ovf);
   else
-    k_root_final<double><<<1, 64, 0, s>>>((const double *)partial, nblk, b, (double *)out, ovf);
+    k_root_final<double><<<blocks, 64, 0, s>>>((const double *)partial, nblk, b, (double *)out, ovf);
 }
 
 void launch_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *colors, int64_t n,

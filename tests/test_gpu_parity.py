@@ -381,3 +381,48 @@ def test_large_k_on_complete_graph(par, k):
         assert int(ru["colorful_u64"][j]) == exact % (1 << 64)
         assert r64["colorful"][j] == pytest.approx(float(exact), rel=FP64_TOL)
         assert r32["colorful"][j] == pytest.approx(float(exact), rel=FP32_TOL)
+
+
+def test_gpu_estimator_is_unbiased():
+    """End to end on the GPU: the mean of colourful/(P alpha) over 2000
+    colourings (FP32, batched) is within 4 standard errors of the number of
+    copies of the template counted by brute force (Sec. 2.2.2), for k = t and
+    k > t; every colouring's count equals the oracle's on the same colouring."""
+    rng = np.random.default_rng(4)
+    n = 40
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < 0.12]
+    G = gg.from_edge_list(n, edges)
+    g = sg.Graph.from_csr(G)
+    for par, k in ((gg.PATH5, 5), ([-1, 0, 0, 1, 1], 5), (gg.PATH5, 7)):
+        alpha = O.automorphisms(par)
+        _, maps, _ = O.brute(G, par, None)
+        copies = maps / alpha
+        N = 2000
+        r = sg.count(sg.Plan(par, k), g, sg.Colorings(g, k, 123, N), "fp32s")
+        est = np.asarray(r["estimate"])
+        se = est.std(ddof=1) / math.sqrt(N)
+        say("estimator", par, k, copies, est.mean(), se)
+        assert abs(est.mean() - copies) < 4 * se + 1e-9
+        assert r["mean_estimate"] == pytest.approx(est.mean(), rel=1e-12)
+        for j in (0, 1, N - 1):
+            f = O.count(G, par, k, O.colors(G.n, k, 123, j))[0]
+            assert r["colorful"][j] == pytest.approx(f, rel=FP32_TOL)
+
+
+@pytest.mark.parametrize("mode", ["u64", "fp64", "fp32s"])
+def test_many_colourings_per_pass(mode):
+    """Small templates batch hundreds of colourings per pass (colourings as
+    extra table columns); every one of 300 colourings matches the oracle."""
+    rng = np.random.default_rng(8)
+    n = 60
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < 0.1]
+    G = gg.from_edge_list(n, edges)
+    g = sg.Graph.from_csr(G)
+    par, k, N = gg.PATH5, 5, 300
+    r = sg.count(sg.Plan(par, k), g, sg.Colorings(g, k, 42, N), mode)
+    for j in range(N):
+        f, u, _ = O.count(G, par, k, O.colors(G.n, k, 42, j), mode=O.U64)
+        if mode == "u64":
+            assert int(r["colorful_u64"][j]) == u, j
+        else:
+            assert r["colorful"][j] == pytest.approx(float(u), rel=FP64_TOL if mode == "fp64" else FP32_TOL), j
