@@ -923,7 +923,8 @@ sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t 
   }
   const int64_t chunks = (nc + W - 1) / W;
   const double per_chunk = (double)kXsplit * U->x_tasks * W * x.es;
-  const int64_t gch = std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)((4.0 * (1 << 30)) / per_chunk)));
+  const int64_t gch = std::max<int64_t>(
+      1, std::min<int64_t>({chunks, (int64_t)65535, (int64_t)((4.0 * (1 << 30)) / per_chunk)}));
   ST_TRY(x.ws->xpart.ensure((size_t)(per_chunk * gch) + 256));
   *group = gch;
   return SG2V_OK;
@@ -995,13 +996,19 @@ sg2v_status step_spmm(Ctx &x, int node) {
   const double bytes = 2.0 * n * (double)nc * x.es +
                        (double)chunks * (nnz * (4.0 + (x.g->w ? 4.0 : 0.0)) + 20.0 * x.g->n_tasks);
   if (gch == 0) {
-    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
-              (unsigned)chunks);
-    ProfScope ps(SG2V_K_SPMM, bytes, nnz * (double)nc, x.s);
-    if (launch_spmm(x.dt, a, x.pp.G, unroll, grid, x.s)) {
-      set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
-      return SG2V_EINVAL;
+    // all chunks in one launch (grid.y is at most 65535: groups beyond that)
+    for (int64_t c0 = 0; c0 < chunks; c0 += 65535) {
+      const int64_t gc = std::min<int64_t>(65535, chunks - c0);
+      const double frac = (double)gc / (double)chunks;
+      a.chunk0 = c0;
+      dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)), (unsigned)gc);
+      ProfScope ps(SG2V_K_SPMM, bytes * frac, nnz * (double)nc * frac, x.s);
+      if (launch_spmm(x.dt, a, x.pp.G, unroll, grid, x.s)) {
+        set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
+        return SG2V_EINVAL;
+      }
     }
+    a.chunk0 = 0;
   } else {
     // long tasks split over the XCDs' neighbour ranges, chunk group by group
     unsigned *mx = a.mx;
@@ -1406,7 +1413,7 @@ int choose_batch(const Plan &P, int ncol, int dt, int64_t n, int64_t n_slots) {
   for (auto &nd : P.nodes)
     if (nd.n_passive_uses > 0) widest_passive = std::max(widest_passive, nd.size == 1 ? P.k : nd.cols);
   int b = tu.batch > 0 ? tu.batch : (int)std::max<int64_t>(1, 1024 / widest_passive);
-  b = std::max(1, std::min(b, ncol));
+  b = std::max(1, std::min({b, ncol, 65535}));  // colourings of a pass index grid.y
   // memory budget
   size_t fr = 0, tot = 0;
   (void)hipMemGetInfo(&fr, &tot);
