@@ -272,7 +272,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU "
-                          "sharding of the count is a design, not part of this build",
+                          "sharding of the count is described, not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
