@@ -341,11 +341,18 @@ __global__ void __launch_bounds__(BLOCK) k_xsplit_combine(XsplitCombineArgs a) {
 #pragma unroll
   for (int u = 0; u < N; ++u) cmax[u] = T(0);
   for (int64_t t = blockIdx.y; t < a.n_tasks; t += gridDim.y) {
-    V16<T> acc = *(const V16<T> *)(P + t * a.ldp + cl);
-    for (int x = 1; x < a.xsplit; ++x) {
-      const V16<T> w = *(const V16<T> *)(P + ((int64_t)x * a.n_tasks + t) * a.ldp + cl);
+    // the eight range partials are loaded together, then summed in range order
+    V16<T> w[8];
 #pragma unroll
-      for (int u = 0; u < N; ++u) acc.x[u] = A::add(acc.x[u], w.x[u], ovf);
+    for (int x = 0; x < 8; ++x)
+      if (x < a.xsplit) w[x] = *(const V16<T> *)(P + ((int64_t)x * a.n_tasks + t) * a.ldp + cl);
+    V16<T> acc = w[0];
+#pragma unroll
+    for (int x = 1; x < 8; ++x) {
+      if (x < a.xsplit) {
+#pragma unroll
+        for (int u = 0; u < N; ++u) acc.x[u] = A::add(acc.x[u], w[x].x[u], ovf);
+      }
     }
     const int slot = a.task_slot[t];
     if (slot < 0) {

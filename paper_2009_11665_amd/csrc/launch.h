@@ -75,7 +75,7 @@ struct SpmmArgs {
 
 struct XsplitCombineArgs {
   const void *partial8;  // [xsplit][n_tasks][ldp]
-  int32_t xsplit;
+  int32_t xsplit;        // 1..8
   int64_t n_tasks, ldp;
   int64_t col_first;     // column of B where this chunk group starts
   const int32_t *task_row, *task_slot;

@@ -58,6 +58,7 @@ constexpr int kPersistBlocks = 2048;
 constexpr int kRootBlocks = 2048;    // most root blocks (per-block partial sums)
 constexpr int kXsplit = 8;          // neighbour ranges (one per XCD)
 constexpr int64_t kXsplitMin = 512; // tasks at least this long are split by range
+constexpr double kXpartBytes = 8.0 * (1 << 30);  // range-partial rows of one chunk group
 // graphs whose 128-byte column chunk (n rows) reaches 32 MB: wider chunks and
 // the neighbour-range split by default
 bool large_graph(int64_t n) { return (double)n * 128.0 >= 32.0 * (1 << 20); }
@@ -924,7 +925,7 @@ sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t 
   const int64_t chunks = (nc + W - 1) / W;
   const double per_chunk = (double)kXsplit * U->x_tasks * W * x.es;
   const int64_t gch = std::max<int64_t>(
-      1, std::min<int64_t>({chunks, (int64_t)65535, (int64_t)((4.0 * (1 << 30)) / per_chunk)}));
+      1, std::min<int64_t>({chunks, (int64_t)65535, (int64_t)(kXpartBytes / per_chunk)}));
   ST_TRY(x.ws->xpart.ensure((size_t)(per_chunk * gch) + 256));
   *group = gch;
   return SG2V_OK;
