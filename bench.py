@@ -138,25 +138,33 @@ def write_traffic(spmm_fetch, spmm_write, copy_fetch, copy_write, copy_mib):
 
 def batch_workload(sg, gg, torch, reps=3):
     """Three templates of uneven size (bintree7, path8, caterpillar10, k = t)
-    x 16 colourings on Chung-Lu n = 500,000, mean degree 20: all passes of all
-    templates recorded as one HIP graph (sg2v_count_batch, replayed), against
-    the same counts run template by template, colouring included.  Tuning
-    from the autotuner on the widest template."""
+    x 16 colourings on Chung-Lu n = 500,000, mean degree 20, each template
+    re-rooted by sg2v_template_reroot (same counts, cheaper decomposition):
+    all passes of all templates recorded as one HIP graph (sg2v_count_batch,
+    replayed), against the same counts run template by template, colouring
+    included, and against the templates rooted as given.  Tuning from the
+    autotuner on the widest template."""
     G = gg.chung_lu_500k()
     g = sg.Graph.from_csr(G)
-    pars = (gg.BINTREE7, gg.PATH8, gg.CATERPILLAR10)
+    given = (gg.BINTREE7, gg.PATH8, gg.CATERPILLAR10)
+    pars = [sg.reroot(p, len(p), 0.05)[0] for p in given]
     plans = [sg.Plan(p) for p in pars]
     ncol, seed = 16, 4
     old = sg.get_tuning()
-    try:
-        tuned = sg.autotune(plans[2], g, "fp32s", 2)
-        sg.count_batch(plans, g, seed, ncol, "fp32s")  # records and caches the graph
+
+    def graph_ms(pl):
+        sg.count_batch(pl, g, seed, ncol, "fp32s")  # records and caches the graph
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            cf, _ = sg.count_batch(plans, g, seed, ncol, "fp32s")
+            cf, _ = sg.count_batch(pl, g, seed, ncol, "fp32s")
         torch.cuda.synchronize()
-        t_graph = (time.perf_counter() - t0) / reps
+        return (time.perf_counter() - t0) / reps, cf
+
+    try:
+        tuned = sg.autotune(plans[2], g, "fp32s", 2)
+        t_given, cf_given = graph_ms([sg.Plan(p) for p in given])
+        t_graph, cf = graph_ms(plans)
         for p, par in zip(plans, pars):  # warm
             sg.count(p, g, sg.Colorings(g, len(par), seed, ncol), "fp32s")
         torch.cuda.synchronize()
@@ -169,10 +177,13 @@ def batch_workload(sg, gg, torch, reps=3):
     finally:
         sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
     return {
-        "workload": "chung-lu n=500000 d=20 gamma=2.1; bintree7, path8, caterpillar10 (k=t) x 16 colourings, fp32s",
+        "workload": "chung-lu n=500000 d=20 gamma=2.1; bintree7, path8, caterpillar10 (k=t, re-rooted) x 16 colourings, fp32s",
         "template_colorings_per_s": 3 * ncol / t_graph,
         "ms_one_graph_launch": t_graph * 1e3,
         "ms_template_by_template": t_seq * 1e3,
+        "ms_one_graph_launch_given_roots": t_given * 1e3,
+        "rerooted_vs_given_max_rel_diff": float(max(abs(a - b) / abs(b) for a, b in zip(cf.ravel(), cf_given.ravel()))),
+        "parents": pars,
         "tuning": {"spmm_width": tuned.spmm_width, "ema_rows": tuned.ema_rows, "batch": tuned.batch,
                    "flags": tuned.flags},
     }

@@ -81,6 +81,28 @@ const char *sg2v_version(void);
 sg2v_status sg2v_plan_create(const int32_t *parent, int32_t t, int32_t k, sg2v_plan **out);
 void sg2v_plan_destroy(sg2v_plan *plan);
 
+/* An isomorphic copy of T whose decomposition (Sec. 2.3.2) costs less; host
+ * only.  The colourful count sums rooted counts over every image of the root,
+ * so it is the number of colourful injective maps of T: it depends neither on
+ * the root nor on the order in which a vertex's children are cut, and alpha is
+ * |Aut| of the unrooted tree.  Every vertex is tried as the root; for each, every
+ * vertex's children are ordered to minimise that vertex's multiply-add work
+ * (all distinct orders of isomorphic-child classes up to 8! of them, else by
+ * increasing subtree size).  The root minimising
+ *   spmm_weight * sum over distinct passive subtrees (>= 2 vertices) of C(k, |T_p|)
+ *   + sum over distinct splits of C(k, |T_s|) C(|T_s|, |T_a|)
+ *     (the root split: C(k, |T_a|), its root reduction)
+ * is kept, the given root winning ties.  spmm_weight is the cost of one
+ * aggregated column per vertex relative to one multiply-add pair per vertex:
+ * about 0.5 on graphs of mean degree 200, less on sparser graphs.
+ *   parent     : host, t entries (as sg2v_plan_create).
+ *   parent_out : host, t entries: the relabelled tree (root 0, children of a
+ *                vertex numbered in their chosen cut order, breadth first).
+ *   perm_out   : host, t entries or NULL: perm_out[v] = new label of vertex v.
+ * Errors: EINVAL (null, negative weight), ENOTTREE, ERANGE (t, k). */
+sg2v_status sg2v_template_reroot(const int32_t *parent, int32_t t, int32_t k, double spmm_weight,
+                                 int32_t *parent_out, int32_t *perm_out);
+
 typedef struct {
   int32_t t;              /* template vertices */
   int32_t k;              /* colours */
@@ -254,6 +276,8 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
                                     get 256-byte chunks in any case) */
 #define SG2V_TUNE_ROOT_ROWS 64   /* root reduction one vertex per block step in vertex order instead
                                     of colour by colour with double-buffered rows */
+#define SG2V_TUNE_ROOT_THREAD 256 /* narrow root tables read by one thread per vertex from global
+                                     memory instead of staged in LDS a tile of rows at a time */
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;

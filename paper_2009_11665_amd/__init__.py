@@ -62,6 +62,7 @@ class Tuning(ctypes.Structure):
 
 
 EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_destroy",
+           "sg2v_template_reroot",
            "sg2v_plan_info", "sg2v_plan_node", "sg2v_plan_pairs", "sg2v_graph_create", "sg2v_graph_destroy",
            "sg2v_color", "sg2v_colorings_destroy", "sg2v_colorings_download", "sg2v_count",
            "sg2v_count_batch", "sg2v_count_grad", "sg2v_debug_table", "sg2v_set_tuning",
@@ -96,6 +97,7 @@ def lib():
         L.sg2v_version.restype = ctypes.c_char_p
         L.sg2v_plan_create.argtypes = [P, i32, i32, ctypes.POINTER(P)]
         L.sg2v_plan_destroy.argtypes = [P]
+        L.sg2v_template_reroot.argtypes = [P, i32, i32, ctypes.c_double, P, P]
         L.sg2v_plan_destroy.restype = None
         L.sg2v_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
         L.sg2v_plan_node.argtypes = [P, i32, ctypes.POINTER(NodeInfo)]
@@ -149,6 +151,18 @@ def _ptr(a):
 
 def version() -> str:
     return lib().sg2v_version().decode()
+
+
+def reroot(parent: Sequence[int], k: Optional[int] = None, spmm_weight: float = 0.5):
+    """Isomorphic template with a cheaper decomposition (sg2v_template_reroot).
+    Returns (parent_out, perm) as lists; counts and estimates are unchanged."""
+    par = np.ascontiguousarray(parent, np.int32)
+    t = len(par)
+    out = np.zeros(t, np.int32)
+    perm = np.zeros(t, np.int32)
+    _check(lib().sg2v_template_reroot(_ptr(par), t, t if k is None else int(k), float(spmm_weight),
+                                      _ptr(out), _ptr(perm)), "sg2v_template_reroot")
+    return [int(x) for x in out], [int(x) for x in perm]
 
 
 class Plan:
@@ -324,6 +338,7 @@ TUNE_NO_XSPLIT = 8
 TUNE_FORCE_XSPLIT = 16
 TUNE_XSPLIT = 32
 TUNE_ROOT_ROWS = 64
+TUNE_ROOT_THREAD = 256
 
 
 def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,

@@ -1191,6 +1191,108 @@ __global__ void __launch_bounds__(BLOCK) k_root_thread(RootArgs a) {
   }
 }
 
+// Root sum for narrow tables (same list as k_root_thread): per tile, R
+// vertex rows of X and Y for colouring blockIdx.y are staged in LDS with
+// consecutive lanes on consecutive columns (coalesced; rows are padded to
+// cpw = 2^lg columns in the lane mapping only), then BLOCK / R lanes per
+// vertex walk its colour's list from LDS.
+// LDS: k * L list words, then R * Cx (and R * Cy) elements of T.
+template <typename T, bool SCALED, bool HASY>
+__global__ void __launch_bounds__(BLOCK) k_root_stage(RootArgs a, int R, int lgx, int lgy) {
+  using A = Arith<T>;
+  using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Acc red[WAVES_PER_BLOCK];
+  uint32_t *lists = (uint32_t *)smem;
+  const int64_t kl = (int64_t)a.k * a.L;
+  T *xs = (T *)(smem + ((kl * 4 + 15) & ~(int64_t)15));
+  T *ys = xs + (int64_t)R * a.Cx;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int j = blockIdx.y;
+  for (int64_t q = threadIdx.x; q < kl; q += BLOCK) lists[q] = a.list16[q];
+  const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
+  const T *X = (const T *)a.X + (int64_t)j * a.Cx;
+  const T *Y = HASY ? (const T *)a.Y + (int64_t)j * a.Cy : nullptr;
+  const float *fx = SCALED ? a.fx + (int64_t)j * a.Cx : nullptr;
+  const float *fy = (SCALED && HASY) ? a.fy + (int64_t)j * a.Cy : nullptr;
+  const int lpv = BLOCK / R;  // lanes per vertex
+  const int r = threadIdx.x / lpv, l = threadIdx.x - r * lpv;
+  bool ovf = false;
+  Acc tot = Acc(0);
+  for (int64_t i0 = (int64_t)blockIdx.x * R; i0 < a.n; i0 += (int64_t)gridDim.x * R) {
+    const int rows = (int)((a.n - i0) < R ? (a.n - i0) : R);
+    __syncthreads();  // lists loaded / previous tile consumed
+    // X slots [0, nx), then Y slots [nx, nx + ny): eight loads in flight per lane
+    const int nx = rows << lgx, ny = HASY ? rows << lgy : 0;
+    for (int q0 = threadIdx.x; q0 < nx + ny; q0 += 8 * BLOCK) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * BLOCK;
+        v[u] = T(0);
+        if (q < nx) {
+          const int rr = q >> lgx, c = q & ((1 << lgx) - 1);
+          if (c < a.Cx) v[u] = X[(i0 + rr) * a.ldx + c];
+        } else if (HASY && q < nx + ny) {
+          const int rr = (q - nx) >> lgy, c = (q - nx) & ((1 << lgy) - 1);
+          if (c < a.Cy) v[u] = Y[(i0 + rr) * a.ldy + c];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * BLOCK;
+        if (q < nx) {
+          const int rr = q >> lgx, c = q & ((1 << lgx) - 1);
+          if (c < a.Cx) {
+            T x = v[u];
+            if constexpr (SCALED) x *= fx[c];
+            xs[rr * a.Cx + c] = x;
+          }
+        } else if (HASY && q < nx + ny) {
+          const int rr = (q - nx) >> lgy, c = (q - nx) & ((1 << lgy) - 1);
+          if (c < a.Cy) {
+            T y = v[u];
+            if constexpr (SCALED) y *= fy[c];
+            ys[rr * a.Cy + c] = y;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (r < rows) {
+      const uint32_t *lc = lists + (int64_t)col[i0 + r] * a.L;
+      const T *xr = xs + r * a.Cx;
+      const T *yr = ys + r * a.Cy;
+      T s = T(0);
+      for (int q = l; q < a.L; q += lpv) {
+        const uint32_t p = lc[q];
+        if constexpr (HASY) s = A::fma(xr[p & 0xFFFFu], yr[p >> 16], s, ovf);
+        else s = A::add(s, xr[p & 0xFFFFu], ovf);
+      }
+      if constexpr (is_u64<Acc>) tot = A::add(tot, s, ovf);
+      else tot += (double)s;
+    }
+  }
+  for (int off = 1; off < WAVE; off <<= 1) {
+    if constexpr (is_u64<Acc>) tot = A::add(tot, shfl_xor(tot, off), ovf);
+    else tot += shfl_xor(tot, off);
+  }
+  if (lane == 0) red[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Acc b = red[0];
+    for (int q = 1; q < WAVES_PER_BLOCK; ++q) {
+      if constexpr (is_u64<Acc>) b = A::add(b, red[q], ovf);
+      else b += red[q];
+    }
+    ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = b;
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+}
+
 template <typename Acc>
 __global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1470,6 +1572,22 @@ static void root_thread_t(const RootArgs &a, dim3 grid, hipStream_t s) {
   const size_t lds = (size_t)a.k * a.L * 4;
   if (a.Y) k_root_thread<T, SC, true><<<grid, BLOCK, lds, s>>>(a);
   else k_root_thread<T, SC, false><<<grid, BLOCK, lds, s>>>(a);
+}
+
+template <typename T, bool SC>
+static void root_stage_t(const RootArgs &a, dim3 grid, int R, size_t lds, hipStream_t s) {
+  int lgx = 0, lgy = 0;
+  while ((1 << lgx) < a.Cx) ++lgx;
+  while ((1 << lgy) < a.Cy) ++lgy;
+  auto kern = a.Y ? k_root_stage<T, SC, true> : k_root_stage<T, SC, false>;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  kern<<<grid, BLOCK, lds, s>>>(a, R, lgx, lgy);
+}
+
+void launch_root_stage(int dtype, const RootArgs &a, dim3 grid, int R, size_t lds, hipStream_t s) {
+  if (dtype == DT_F32) root_stage_t<float, true>(a, grid, R, lds, s);
+  else if (dtype == DT_F64) root_stage_t<double, false>(a, grid, R, lds, s);
+  else root_stage_t<uint64_t, false>(a, grid, R, lds, s);
 }
 
 void launch_root_thread(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) {

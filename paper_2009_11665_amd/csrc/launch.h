@@ -218,6 +218,10 @@ void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStr
 void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, bool db, hipStream_t s);
 // one thread per vertex; needs list16, k * L <= 8192 (lists staged in LDS)
 void launch_root_thread(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
+// R vertex rows staged per tile (R a power of two dividing BLOCK); needs
+// list16, Cx, Cy <= 65536 and lds = k * L * 4 (rounded up to 16) + R * (Cx +
+// Cy) * element size
+void launch_root_stage(int dtype, const RootArgs &a, dim3 grid, int R, size_t lds, hipStream_t s);
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s);
 void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,

@@ -439,6 +439,210 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
   return SG2V_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Choice of root and cut order (Sec. 2.3.2).  The colourful count sums the
+// rooted counts over every image of the root, so it is the number of
+// colourful injective maps of T and does not depend on which vertex is the
+// root or in which order a vertex's children are cut; alpha is |Aut| of the
+// unrooted tree.  Only the work of the decomposition changes.
+
+namespace {
+
+struct Rooted {
+  int r = 0;
+  std::vector<std::vector<int>> ch;  // children, in the order they are kept
+  std::vector<int> size;
+  std::vector<std::string> canon;    // AHU string of the full subtree
+  std::vector<int> bfs;
+};
+
+Rooted root_at(const std::vector<std::vector<int>> &adj, int r) {
+  const int t = (int)adj.size();
+  Rooted R;
+  R.r = r;
+  R.ch.assign(t, {});
+  R.size.assign(t, 1);
+  R.canon.assign(t, "");
+  std::vector<int> par(t, -2);
+  par[r] = -1;
+  R.bfs.push_back(r);
+  for (size_t q = 0; q < R.bfs.size(); ++q) {
+    const int v = R.bfs[q];
+    for (int u : adj[v])
+      if (par[u] == -2) {
+        par[u] = v;
+        R.ch[v].push_back(u);
+        R.bfs.push_back(u);
+      }
+  }
+  for (int q = t - 1; q >= 0; --q) {
+    const int v = R.bfs[q];
+    std::vector<std::string> kids;
+    for (int u : R.ch[v]) {
+      R.size[v] += R.size[u];
+      kids.push_back(R.canon[u]);
+    }
+    std::sort(kids.begin(), kids.end());
+    std::string s = "(";
+    for (auto &x : kids) s += x;
+    R.canon[v] = s + ")";
+  }
+  return R;
+}
+
+// Work of vertex v's splits for one child order: node (v, n) multiplies
+// C(k, s_n) * C(s_n, s_{n-1}) pairs per vertex, s_n = 1 + sizes of the first
+// n children; the last split of the root is its root reduction, C(k, s_{d-1}).
+double local_pairs(const Rooted &R, int v, const std::vector<int> &order, int k) {
+  double c = 0;
+  int s = 1;
+  for (size_t n = 0; n < order.size(); ++n) {
+    const int s1 = s + R.size[order[n]];
+    if (v == R.r && n + 1 == order.size()) c += (double)binom(k, s);
+    else c += (double)binom(k, s1) * (double)binom(s1, s);
+    s = s1;
+  }
+  return c;
+}
+
+// Per vertex, the child order with the least local work (every distinct order
+// of the isomorphism classes while there are at most 8! of them, else by
+// increasing subtree size); ties keep the current order.
+void choose_orders(Rooted &R, int k) {
+  for (size_t v = 0; v < R.ch.size(); ++v) {
+    std::vector<int> &ch = R.ch[v];
+    if (ch.size() < 2) continue;
+    std::vector<int> best = ch;
+    double best_c = local_pairs(R, (int)v, ch, k);
+    std::vector<int> idx(ch.size());
+    for (size_t i = 0; i < ch.size(); ++i) idx[i] = (int)i;
+    auto cls = [&](int i) -> const std::string & { return R.canon[ch[i]]; };
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return cls(a) < cls(b) || (cls(a) == cls(b) && a < b); });
+    double perms = 1;
+    for (size_t i = 2; i <= ch.size(); ++i) perms *= (double)i;
+    std::vector<int> order(ch.size());
+    if (perms <= 40320.0) {
+      // distinct arrangements of the class sequence: permute class labels
+      std::vector<int> lab(ch.size());
+      for (size_t i = 0; i < idx.size(); ++i)
+        lab[i] = (i > 0 && cls(idx[i]) == cls(idx[i - 1])) ? lab[i - 1] : (int)i;
+      std::vector<int> seq = lab;
+      do {
+        // the p-th member of a class goes to its p-th occurrence in seq
+        std::map<int, int> used;
+        for (size_t i = 0; i < seq.size(); ++i) {
+          int p = used[seq[i]]++;
+          order[i] = ch[idx[seq[i] + p]];
+        }
+        const double c = local_pairs(R, (int)v, order, k);
+        if (c < best_c) {
+          best_c = c;
+          best = order;
+        }
+      } while (std::next_permutation(seq.begin(), seq.end()));
+    } else {
+      order = ch;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return R.size[a] < R.size[b]; });
+      const double c = local_pairs(R, (int)v, order, k);
+      if (c < best_c) best = order;
+    }
+    ch = best;
+  }
+}
+
+// Total work of the rooted, ordered tree with isomorphic sub-templates
+// counted once (as the planner shares their tables).
+double decomposition_cost(const Rooted &R, int k, double spmm_weight) {
+  std::map<std::string, int> seen;  // kept-children key -> size
+  std::map<std::string, int> passive;
+  double pairs = 0;
+  std::function<int(int, int, std::string *)> build = [&](int v, int n, std::string *key_out) -> int {
+    std::vector<std::string> kids;
+    for (int i = 0; i < n; ++i) kids.push_back(R.canon[R.ch[v][i]]);
+    std::sort(kids.begin(), kids.end());
+    std::string key = "(";
+    for (auto &x : kids) key += x;
+    key += ")";
+    if (key_out) *key_out = key;
+    auto it = seen.find(key);
+    if (it != seen.end()) return it->second;
+    int s = 1;
+    if (n > 0) {
+      const int tau = R.ch[v][n - 1];
+      const int sa = build(v, n - 1, nullptr);
+      std::string pk;
+      const int sp = build(tau, (int)R.ch[tau].size(), &pk);
+      s = sa + sp;
+      if (sp >= 2) passive[pk] = sp;
+      if (v == R.r && n == (int)R.ch[v].size()) pairs += (double)binom(k, sa);
+      else pairs += (double)binom(k, s) * (double)binom(s, sa);
+    }
+    seen[key] = s;
+    return s;
+  };
+  build(R.r, (int)R.ch[R.r].size(), nullptr);
+  double cols = 0;
+  for (auto &p : passive) cols += (double)binom(k, p.second);
+  return spmm_weight * cols + pairs;
+}
+
+}  // namespace
+
+sg2v_status template_reroot(const int32_t *parent, int t, int k, double spmm_weight,
+                            int32_t *parent_out, int32_t *perm_out) {
+  if (!parent || !parent_out) {
+    set_error("sg2v_template_reroot: null argument");
+    return SG2V_EINVAL;
+  }
+  if (t < 1 || k < t || k > SG2V_KMAX) {
+    set_error("sg2v_template_reroot: need 1 <= t <= k <= %d (t=%d, k=%d)", SG2V_KMAX, t, k);
+    return SG2V_ERANGE;
+  }
+  if (!(spmm_weight >= 0.0)) {
+    set_error("sg2v_template_reroot: spmm_weight must be >= 0");
+    return SG2V_EINVAL;
+  }
+  Tree T;
+  sg2v_status st = tree_from_parent(parent, t, T);
+  if (st != SG2V_OK) return st;
+  std::vector<std::vector<int>> adj(t);
+  for (int v = 0; v < t; ++v)
+    if (v != T.root) {
+      adj[v].push_back(parent[v]);
+      adj[parent[v]].push_back(v);
+    }
+  for (auto &a : adj) std::sort(a.begin(), a.end());
+  // the given root first, so that ties keep it
+  Rooted best = root_at(adj, T.root);
+  choose_orders(best, k);
+  double best_c = decomposition_cost(best, k, spmm_weight);
+  for (int r = 0; r < t; ++r) {
+    if (r == T.root) continue;
+    Rooted R = root_at(adj, r);
+    choose_orders(R, k);
+    const double c = decomposition_cost(R, k, spmm_weight);
+    if (c < best_c) {
+      best_c = c;
+      best = std::move(R);
+    }
+  }
+  // relabel breadth first, children in their chosen order, root 0
+  std::vector<int> lab(t, -1), order{best.r};
+  lab[best.r] = 0;
+  for (size_t q = 0; q < order.size(); ++q)
+    for (int u : best.ch[order[q]]) {
+      lab[u] = (int)order.size();
+      order.push_back(u);
+    }
+  parent_out[0] = -1;
+  for (int v : order)
+    for (int u : best.ch[v]) parent_out[lab[u]] = lab[v];
+  if (perm_out)
+    for (int v = 0; v < t; ++v) perm_out[v] = lab[v];
+  return SG2V_OK;
+}
+
 }  // namespace sg2v
 
 using namespace sg2v;
@@ -466,6 +670,16 @@ sg2v_status sg2v_plan_create(const int32_t *parent, int32_t t, int32_t k, sg2v_p
     return SG2V_OK;
   } catch (const std::bad_alloc &) {
     set_error("sg2v_plan_create: out of host memory");
+    return SG2V_ENOMEM;
+  }
+}
+
+sg2v_status sg2v_template_reroot(const int32_t *parent, int32_t t, int32_t k, double spmm_weight,
+                                 int32_t *parent_out, int32_t *perm_out) {
+  try {
+    return template_reroot(parent, t, k, spmm_weight, parent_out, perm_out);
+  } catch (const std::bad_alloc &) {
+    set_error("sg2v_template_reroot: out of host memory");
     return SG2V_ENOMEM;
   }
 }

@@ -1306,8 +1306,20 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   // narrow rows and short lists: one thread per vertex
   const bool use_thread = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && P.root_L <= 256 &&
                           (int64_t)P.k * P.root_L <= 8192 && X->cols <= 512 && (!Y || Y->cols <= 512);
+  // narrow rows: a tile of rows staged in LDS, a few lanes per vertex
+  int stage_R = 0;
+  size_t stage_lds = 0;
+  if (use_thread && !(tuning().flags & SG2V_TUNE_ROOT_THREAD)) {
+    const size_t lists = (size_t)round_up((int64_t)P.k * P.root_L * 4, 16);
+    const size_t per_row = (size_t)(X->cols + (Y ? Y->cols : 0)) * x.es;
+    for (int R = 64; R >= 4 && !stage_R; R /= 2)
+      if (lists + R * per_row <= 48 * 1024) stage_R = R;
+    stage_lds = lists + (size_t)stage_R * per_row;
+  }
   int nblk = 1024;
-  if (use_thread)
+  if (stage_R)
+    nblk = (int)std::min<int64_t>(kRootBlocks, std::max<int64_t>(1, (x.g->n + stage_R - 1) / stage_R));
+  else if (use_thread)
     nblk = (int)std::min<int64_t>(kRootBlocks, std::max<int64_t>(1, (x.g->n + 255) / 256));
   else if (use_tile)
     nblk = (int)std::min<int64_t>(kRootBlocks, (int64_t)x.cu_count *
@@ -1316,7 +1328,8 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
     ProfScope ps(SG2V_K_ROOT,
                  (double)x.g->n * x.b * (double)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es,
                  (double)x.g->n * x.b * (double)P.root_L, x.s);
-    if (use_thread) launch_root_thread(x.dt, a, dim3(nblk, x.b), x.s);
+    if (stage_R) launch_root_stage(x.dt, a, dim3(nblk, x.b), stage_R, stage_lds, x.s);
+    else if (use_thread) launch_root_thread(x.dt, a, dim3(nblk, x.b), x.s);
     else if (use_tile) launch_root_tile(x.dt, a, dim3(nblk, x.b), tile_lds, tile_db, x.s);
     else if (use_lds) launch_root_lds(x.dt, a, dim3(nblk, x.b), stage, x.s);
     else launch_root(x.dt, a, dim3(nblk, x.b), x.s);

@@ -143,3 +143,78 @@ def test_tuning_roundtrip():
         assert (t.spmm_width, t.ema_rows, t.batch, t.budget_bytes) == (64, 8, 3, 123456)
     finally:
         sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+
+
+def _edges(par):
+    return {frozenset((v, p)) for v, p in enumerate(par) if p >= 0}
+
+
+def _random_tree(t, rng):
+    par = [-1] + [int(rng.integers(0, v)) for v in range(1, t)]
+    perm = rng.permutation(t)
+    out = [0] * t
+    for v in range(t):
+        out[perm[v]] = -1 if par[v] < 0 else int(perm[par[v]])
+    return out
+
+
+REROOT_CASES = TEMPLATES + [_random_tree(t, np.random.default_rng(t)) for t in (6, 9, 12, 14)]
+
+
+@pytest.mark.parametrize("par", REROOT_CASES)
+def test_reroot_is_a_relabelling_with_no_more_work(par):
+    """sg2v_template_reroot returns the same tree under a vertex bijection
+    (edges map to edges), rooted at 0 with children numbered after their
+    parent, and a decomposition whose work (aggregated columns, multiply-add
+    pairs) does not exceed the input's for any column weight."""
+    t = len(par)
+    k = min(t + 1, 20)
+    for w in (0.0, 0.5, 4.0):
+        out, perm = sg.reroot(par, k, w)
+        assert sorted(perm) == list(range(t))
+        assert out[0] == -1 and all(0 <= out[v] < v for v in range(1, t))
+        assert {frozenset((perm[a], perm[b])) for a, b in map(tuple, _edges(par))} == _edges(out)
+        a, b = sg.Plan(par, k).info(), sg.Plan(out, k).info()
+        assert b.alpha == a.alpha == O.automorphisms(out)
+        assert w * b.spmm_columns + b.pairs_per_vertex <= w * a.spmm_columns + a.pairs_per_vertex + 1e-9
+
+
+def test_reroot_twenty_vertices_is_a_relabelling():
+    for seed in range(4):
+        par = _random_tree(20, np.random.default_rng(100 + seed))
+        out, perm = sg.reroot(par, 20, 0.5)
+        assert sorted(perm) == list(range(20)) and out[0] == -1
+        assert {frozenset((perm[a], perm[b])) for a, b in map(tuple, _edges(par))} == _edges(out)
+        assert O.automorphisms(out) == O.automorphisms(par)
+
+
+def test_reroot_moves_path_root_to_the_middle():
+    out, _ = sg.reroot(gg.PATH8, 8, 0.5)
+    root_kids = [v for v in range(8) if out[v] == 0]
+    assert len(root_kids) == 2  # an inner vertex, not an end
+    p0, p1 = sg.Plan(gg.PATH8, 8).info(), sg.Plan(out, 8).info()
+    assert p1.spmm_columns < p0.spmm_columns and p1.pairs_per_vertex < p0.pairs_per_vertex
+    # the complete binary tree is already best rooted at its centre
+    out, _ = sg.reroot(gg.BINTREE15, 15, 0.5)
+    assert sg.Plan(out, 15).info().spmm_columns == sg.Plan(gg.BINTREE15, 15).info().spmm_columns
+
+
+@pytest.mark.parametrize("par", [gg.PATH8, gg.CATERPILLAR10, _random_tree(9, np.random.default_rng(3))])
+def test_reroot_keeps_the_colourful_count(par):
+    """The colourful count of the relabelled template equals the input's
+    (exact, by the oracle, which decomposes each rooting on its own)."""
+    G = gg.tiny_er(4)
+    t = len(par)
+    out, _ = sg.reroot(par, t, 0.5)
+    for j in range(2):
+        col = O.colors(G.n, t, 11, j)
+        assert O.count(G, par, t, col, mode=O.U64)[1] == O.count(G, out, t, col, mode=O.U64)[1]
+
+
+def test_reroot_rejects_bad_input():
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.reroot([-1, 2, 1], 3)
+    assert e.value.status == -2
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.reroot([-1, 0], 2, -1.0)
+    assert e.value.status == -1

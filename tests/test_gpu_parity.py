@@ -95,6 +95,44 @@ def test_templates_u64_exact(small_rmat, ti):
         assert r["overflow"] == any(x[2] for x in oracle_counts(small_rmat, par, k, 5, 3, O.U64))
 
 
+@pytest.mark.parametrize("flags", [0, 256])
+@pytest.mark.parametrize("par", [gg.PATH8, gg.CATERPILLAR10, random_tree(12, np.random.default_rng(8))])
+def test_rerooted_template_same_counts(small_rmat, par, flags):
+    """A template re-rooted by sg2v_template_reroot counts exactly what the
+    oracle counts for the template as given (U64), FP64 and FP32S agree; the
+    narrow root tables go through the staged root (flags 0) or the
+    thread-per-vertex root (ROOT_THREAD)."""
+    t = len(par)
+    out, _ = sg.reroot(par, t, 0.5)
+    say("rerooted", par, "->", out, "flags", flags)
+    ref = oracle_counts(small_rmat, par, t, 9, 2, O.U64)
+    old = sg.get_tuning()
+    try:
+        sg.set_tuning(flags=flags)
+        r = gpu_counts(small_rmat, out, t, 9, 2, "u64")
+        for j in range(2):
+            assert int(r["colorful_u64"][j]) == ref[j][1]
+        for mode, tol in (("fp64", FP64_TOL), ("fp32s", FP32_TOL)):
+            rf = gpu_counts(small_rmat, out, t, 9, 2, mode)
+            for j in range(2):
+                assert rf["colorful"][j] == pytest.approx(float(ref[j][1]), rel=tol)
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+
+
+def test_staged_root_several_tiles_per_block():
+    """262,144 vertices: more row tiles than root blocks, so every block
+    walks several tiles (path8 re-rooted: distinct narrow X and Y)."""
+    G = gg.rmat(18, 600_000, seed=13)
+    out, _ = sg.reroot(gg.PATH8, 8, 0.5)
+    ref = oracle_counts(G, gg.PATH8, 8, 4, 1, O.U64)
+    say("staged root rmat18 path8")
+    r = gpu_counts(G, out, 8, 4, 1, "u64")
+    assert int(r["colorful_u64"][0]) == ref[0][1]
+    r = gpu_counts(G, out, 8, 4, 1, "fp32s")
+    assert r["colorful"][0] == pytest.approx(float(ref[0][1]), rel=FP32_TOL)
+
+
 def test_random_trees_all_modes(small_rmat):
     rng = np.random.default_rng(5)
     for _ in range(6):
@@ -212,7 +250,7 @@ def test_spmm_widths_agree(small_rmat):
                        sg.TUNE_FORCE_XSPLIT, sg.TUNE_FORCE_XSPLIT | sg.TUNE_NO_COLOR_SKIP,
                        sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA | sg.TUNE_SPMM_UNROLL4,
                        sg.TUNE_XSPLIT, sg.TUNE_ROOT_ROWS, sg.TUNE_SPMM_UNROLL8,
-                       sg.TUNE_SPMM_UNROLL8 | sg.TUNE_FORCE_XSPLIT):
+                       sg.TUNE_SPMM_UNROLL8 | sg.TUNE_FORCE_XSPLIT, sg.TUNE_ROOT_THREAD):
                 sg.set_tuning(spmm_width=w, flags=fl)
                 say("spmm width", w, "flags", fl)
                 got = sg.count(p, g, c, "u64")["colorful_u64"]
