@@ -254,7 +254,8 @@ typedef struct {
 sg2v_status sg2v_profile_start(void);
 sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
 
-/* Tuning knobs (0 = automatic).  spmm_width: columns per SpMM chunk;
+/* Tuning knobs (0 = automatic).  spmm_width: columns per SpMM chunk (row
+ * segments of 2 to 32 lanes of 16 bytes: up to 128 FP32 or 64 FP64 columns);
  * ema_rows: rows per eMA tile; batch: colourings per pass; flags:
  * SG2V_TUNE_NO_COLOR_SKIP disables the colour-based skipping of SpMM row
  * segments, SG2V_TUNE_NO_COLOR_EMA the colour-restricted multiply-add

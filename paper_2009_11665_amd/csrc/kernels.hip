@@ -1459,6 +1459,7 @@ static int spmm_t(const SpmmArgs &a, int G, dim3 grid, hipStream_t s) {
     case 4: spmm_g<T, 4, UNR>(a, grid, s); return 0;
     case 8: spmm_g<T, 8, UNR>(a, grid, s); return 0;
     case 16: spmm_g<T, 16, UNR>(a, grid, s); return 0;
+    case 32: spmm_g<T, 32, UNR>(a, grid, s); return 0;
     default: return -1;
   }
 }

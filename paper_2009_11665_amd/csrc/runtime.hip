@@ -637,7 +637,7 @@ int pick_G(int dt, int64_t widest_cols_b, int64_t n) {
   sg2v_tuning_t tu = tuning();
   const int N = dt == DT_F32 ? 4 : 2;
   int G = 8;  // 128-byte row segments
-  if (tu.spmm_width > 0) G = std::max(2, std::min(16, tu.spmm_width / N));
+  if (tu.spmm_width > 0) G = std::max(2, std::min(32, tu.spmm_width / N));
   else if (large_graph(n) && !(tu.flags & SG2V_TUNE_NO_XSPLIT)) G = 16;
   // narrow tables: do not read far past the last column
   while (G > 2 && (int64_t)G * N / 2 >= widest_cols_b) G /= 2;

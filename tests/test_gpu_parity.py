@@ -245,7 +245,7 @@ def test_spmm_widths_agree(small_rmat):
     ref = [x[1] for x in oracle_counts(small_rmat, par, k, 2, 2, O.U64)]
     old = sg.get_tuning()
     try:
-        for w in (8, 16, 32, 64):
+        for w in (8, 16, 32, 64, 128):
             for fl in (0, sg.TUNE_NO_COLOR_SKIP, sg.TUNE_NO_COLOR_EMA, sg.TUNE_SPMM_UNROLL4,
                        sg.TUNE_FORCE_XSPLIT, sg.TUNE_FORCE_XSPLIT | sg.TUNE_NO_COLOR_SKIP,
                        sg.TUNE_NO_COLOR_SKIP | sg.TUNE_NO_COLOR_EMA | sg.TUNE_SPMM_UNROLL4,
