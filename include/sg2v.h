@@ -208,8 +208,9 @@ sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n_plans,
  * over its two directed entries.  Tables of each split are recomputed during
  * the backward sweep instead of being stored.
  *   grad_colorful : host, n_colorings doubles.
- *   grad_w        : device, nnz floats (FP32S) or doubles (FP64), written.
- * mode: SG2V_FP64 or SG2V_FP32S.  Errors: EINVAL, ENOMEM, EDEVICE. */
+ *   grad_w        : device, nnz doubles, written.
+ * mode: SG2V_FP64 (the forward tables and the adjoint run in FP64; other
+ * modes are rejected with EINVAL).  Errors: EINVAL, ENOMEM, EDEVICE. */
 sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
                             sg2v_mode mode, const double *grad_colorful, void *grad_w,
                             void *stream);

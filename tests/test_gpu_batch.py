@@ -41,6 +41,27 @@ def test_batch_equals_single_and_oracle():
             np.testing.assert_allclose(est[p], r["estimate"], rtol=1e-12)
 
 
+def test_batch_of_rerooted_templates():
+    """The batch workload's re-rooted templates: the graph-recorded batch
+    equals the oracle's counts of the templates as given (U64), and FP32S
+    agrees with FP64."""
+    G = gg.chung_lu(20_000, 12.0, 2.1, seed=5)
+    g = sg.Graph.from_csr(G)
+    pars = [sg.reroot(p, len(p), 0.05)[0] for p in TEMPLATES]
+    plans = [sg.Plan(p) for p in pars]
+    seed, ncol = 3, 3
+    say("batch rerooted", pars)
+    cu, _ = sg.count_batch(plans, g, seed, ncol, "u64")
+    c64, _ = sg.count_batch(plans, g, seed, ncol, "fp64")
+    c32, _ = sg.count_batch(plans, g, seed, ncol, "fp32s")
+    for p, par in enumerate(TEMPLATES):
+        for j in range(ncol):
+            u = O.count(G, par, len(par), O.colors(G.n, len(par), seed, j), mode=O.U64)[1]
+            assert cu[p][j] == pytest.approx(float(u), rel=1e-15)  # U64 counts returned as float64
+            assert c64[p][j] == pytest.approx(float(u), rel=1e-12)
+            assert c32[p][j] == pytest.approx(float(u), rel=1e-5)
+
+
 def test_batch_graph_replays_with_eager_work_between():
     G = gg.rmat(12, 40_000, seed=9)
     g = sg.Graph.from_csr(G)

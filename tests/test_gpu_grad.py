@@ -153,3 +153,14 @@ def test_autograd_function():
         _, go = O.grad(G, par, k, O.colors(G.n, k, 8, j))
         ref += a * go
     np.testing.assert_allclose(w.grad.double().cpu().numpy(), ref, rtol=1e-6)
+
+
+def test_grad_rejects_modes_other_than_fp64():
+    G = gg.tiny_er()
+    g = sg.Graph.from_csr(G)
+    p = sg.Plan(gg.PATH5, 5)
+    c = sg.Colorings(g, 5, 1, 1)
+    for mode in ("fp32s", "u64"):
+        with pytest.raises(sg.Sg2vError) as e:
+            sg.count_grad(p, g, c, [1.0], mode)
+        assert e.value.status == -1
