@@ -812,20 +812,38 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
   if (track)
     for (int c = threadIdx.x; c < W; c += BLOCK) lmx[c] = 0u;
   __syncthreads();
+  // entry e = r * W + jj * Cs + cl of a tile; a thread starts at e =
+  // threadIdx.x and advances by BLOCK entries, tracked without divisions
+  const int r_first = threadIdx.x / W, cc_first = threadIdx.x - r_first * W;
+  const int jj_first = cc_first / a.Cs, cl_first = cc_first - jj_first * a.Cs;
+  const int dr = BLOCK / W, dcc = BLOCK - dr * W;
+  const int djj = dcc / a.Cs, dcl = dcc - djj * a.Cs;
   for (int64_t i0 = (int64_t)blockIdx.x * R; i0 < a.n; i0 += (int64_t)gridDim.x * R) {
-    const int E = (int)min<int64_t>(R, a.n - i0) * W;  // below 2^31: R * W <= 4 * U * BLOCK + W
+    const int nrow = (int)min<int64_t>(R, a.n - i0);
+    const int E = nrow * W;  // below 2^31: R * W <= 4 * U * BLOCK + W
+    int r = r_first, jc = jj_first, lc = cl_first;
     for (int e0 = threadIdx.x; e0 < E; e0 += U * BLOCK) {
       int64_t row[U];
       int jj[U], cl[U], cc[U], c[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = min(e0 + u * BLOCK, E - 1);
-        const int r = e / W;
-        cc[u] = e - r * W;
-        jj[u] = cc[u] / a.Cs;
-        cl[u] = cc[u] - jj[u] * a.Cs;
-        row[u] = i0 + r;
+        // entries past the tile load from its last row and store nothing
+        row[u] = i0 + min(r, nrow - 1);
+        jj[u] = jc;
+        cl[u] = lc;
+        cc[u] = jc * a.Cs + lc;
         c[u] = a.colors[(int64_t)(a.j0 + jj[u]) * a.n + row[u]];
+        lc += dcl;
+        jc += djj;
+        if (lc >= a.Cs) {
+          lc -= a.Cs;
+          ++jc;
+        }
+        r += dr;
+        if (jc >= a.nb) {
+          jc -= a.nb;
+          ++r;
+        }
       }
       int idx[U];
 #pragma unroll
@@ -856,6 +874,24 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
       if (blockIdx.x == 0) a.es[c] = a.Eb[c / a.Cs];
     }
   }
+}
+
+// FP32S column maxima of a single-vertex-active split, bounded without a pass
+// over the output: M_s(i, C) = B(i, C \ c) f_B(C \ c) for the vertices of a
+// colour c in C, so max_i M_s(i, C) <= max over c in C of mx_B(C \ c) f_B(C \ c)
+// (an upper bound suffices for the frame exponent).  One thread per
+// (colouring, output column).
+__global__ void k_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b, const unsigned *mxB,
+                               const float *fb, unsigned *mx) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)b * Cs) return;
+  const int jj = (int)(q / Cs), C = (int)(q - (int64_t)jj * Cs);
+  float m = 0.f;
+  for (int c = 0; c < k; ++c) {
+    const int d = drop[(int64_t)c * Cs + C];
+    if (d >= 0) m = fmaxf(m, __uint_as_float(mxB[(int64_t)jj * Cb + d]) * fb[(int64_t)jj * Cb + d]);
+  }
+  mx[q] = __float_as_uint(m);
 }
 
 // ===========================================================================
@@ -1695,6 +1731,14 @@ void launch_sddmm(int dtype, const SddmmArgs &a, hipStream_t s) {
   const unsigned g = grid_cap((a.n + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 4096);
   if (dtype == DT_F64) k_sddmm<double><<<g, BLOCK, 0, s>>>(a);
   else if (dtype == DT_F32) k_sddmm<float><<<g, BLOCK, 0, s>>>(a);
+}
+
+void launch_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b, const unsigned *mxB,
+                         const float *fb, unsigned *mx, hipStream_t s) {
+  const int64_t total = (int64_t)b * Cs;
+  if (total == 0) return;
+  k_single_bound<<<grid_cap((total + BLOCK - 1) / BLOCK, 1 << 20), BLOCK, 0, s>>>(drop, k, Cs, Cb, b, mxB, fb,
+                                                                                 mx);
 }
 
 void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t s) {

@@ -232,6 +232,10 @@ void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s);
 void launch_sddmm(int dtype, const SddmmArgs &a, hipStream_t s);
 void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t s);
+// FP32S: mx[j * Cs + C] = an upper bound of the column maxima of a
+// single-vertex-active output from the passive table's maxima and factors
+void launch_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b, const unsigned *mxB,
+                         const float *fb, unsigned *mx, hipStream_t s);
 void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, hipStream_t s);
 
 }  // namespace sg2v

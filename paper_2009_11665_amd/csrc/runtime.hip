@@ -1211,9 +1211,9 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
   // pass over the finished table instead
   // (the single-vertex kernel keeps all b colourings of the pass in a block)
   const size_t lmx_cols = (size_t)nd.cols * (single ? x.b : 1);
-  const bool wide = sc && lmx_cols * 4 > (single ? 48 : 32) * 1024;
-  if (wide) a.mx = nullptr;
-  const size_t lmx = (sc && !wide) ? lmx_cols * 4 : 0;
+  const bool wide = sc && !single && lmx_cols * 4 > 32 * 1024;
+  if (wide || single) a.mx = nullptr;  // single-vertex active: bounded from B's maxima below
+  const size_t lmx = (sc && !wide && !single) ? lmx_cols * 4 : 0;
   if (single) {
     a.nb = x.b;
     const int64_t rows = std::max<int64_t>(1, 8192 / ((int64_t)nd.cols * x.b));
@@ -1222,6 +1222,8 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
     ProfScope ps(SG2V_K_EMA_SINGLE, (double)x.g->n * x.b * (double)(nd.cols + Bt.cols) * x.es,
                  (double)x.g->n * x.b * (double)nd.cols, x.s);
     launch_ema_single(x.dt, a, grid, lmx, x.s);
+    if (sc)
+      launch_single_bound(a.drop, P.k, a.Cs, a.Cb, x.b, Bt.mx, Bt.f, Ms.mx, x.s);
   } else {
     Tab &Ma = x.pp.M[nd.active];
     a.Ma = Ma.p;
