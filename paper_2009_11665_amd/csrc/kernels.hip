@@ -803,14 +803,23 @@ template <typename T, bool SCALED>
 __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
   constexpr int U = 8;
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned *lmx = (unsigned *)smem;  // [nb * Cs] column maxima (FP32S)
   const bool track = SCALED && a.mx != nullptr;
   const int W = a.Cs * a.nb;  // output entries per row
   const int R = max(1, (4 * U * BLOCK) / W);  // rows per tile: about four rounds of loads
+  // LDS: [nb * Cs] column maxima (FP32S, when tracked), the drop table as
+  // uint16 (0xFFFF: C lacks c) when kc > 0, the tile's colours [R][nb]
+  unsigned *lmx = (unsigned *)smem;
+  const int64_t off_drop = track ? ((int64_t)W * 4 + 15) / 16 * 16 : 0;
+  uint16_t *ldrop = (uint16_t *)(smem + off_drop);
+  uint8_t *lcol = smem + off_drop + (a.kc ? ((int64_t)a.kc * a.Cs * 2 + 15) / 16 * 16 : 0);
   const T *Bt = (const T *)a.B;
   T *Ms = (T *)a.Ms;
   if (track)
     for (int c = threadIdx.x; c < W; c += BLOCK) lmx[c] = 0u;
+  for (int q = threadIdx.x; q < a.kc * a.Cs; q += BLOCK) {
+    const int d = a.drop[q];
+    ldrop[q] = d < 0 ? (uint16_t)0xFFFFu : (uint16_t)d;
+  }
   __syncthreads();
   // entry e = r * W + jj * Cs + cl of a tile; a thread starts at e =
   // threadIdx.x and advances by BLOCK entries, tracked without divisions
@@ -821,6 +830,12 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
   for (int64_t i0 = (int64_t)blockIdx.x * R; i0 < a.n; i0 += (int64_t)gridDim.x * R) {
     const int nrow = (int)min<int64_t>(R, a.n - i0);
     const int E = nrow * W;  // below 2^31: R * W <= 4 * U * BLOCK + W
+    __syncthreads();  // previous tile's colours consumed
+    for (int q = threadIdx.x; q < nrow * a.nb; q += BLOCK) {
+      const int rr = q / a.nb, j = q - rr * a.nb;
+      lcol[q] = a.colors[(int64_t)(a.j0 + j) * a.n + i0 + rr];
+    }
+    __syncthreads();
     int r = r_first, jc = jj_first, lc = cl_first;
     for (int e0 = threadIdx.x; e0 < E; e0 += U * BLOCK) {
       int64_t row[U];
@@ -828,11 +843,12 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         // entries past the tile load from its last row and store nothing
-        row[u] = i0 + min(r, nrow - 1);
+        const int rr = min(r, nrow - 1);
+        row[u] = i0 + rr;
         jj[u] = jc;
         cl[u] = lc;
         cc[u] = jc * a.Cs + lc;
-        c[u] = a.colors[(int64_t)(a.j0 + jj[u]) * a.n + row[u]];
+        c[u] = lcol[rr * a.nb + jc];
         lc += dcl;
         jc += djj;
         if (lc >= a.Cs) {
@@ -847,7 +863,14 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
       }
       int idx[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) idx[u] = a.drop[(int64_t)c[u] * a.Cs + cl[u]];
+      for (int u = 0; u < U; ++u) {
+        if (a.kc) {
+          const int d = ldrop[c[u] * a.Cs + cl[u]];
+          idx[u] = d == 0xFFFF ? -1 : d;
+        } else {
+          idx[u] = a.drop[(int64_t)c[u] * a.Cs + cl[u]];
+        }
+      }
       T v[U];
       float f[U];
 #pragma unroll
@@ -1570,15 +1593,18 @@ int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid
 }
 
 void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-  if (dtype == DT_F32) {
-    auto kern = k_ema_single<float, true>;
-    if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    kern<<<grid, BLOCK, lds, s>>>(a);
-  } else if (dtype == DT_F64) {
-    k_ema_single<double, false><<<grid, BLOCK, 0, s>>>(a);
-  } else {
-    k_ema_single<uint64_t, false><<<grid, BLOCK, 0, s>>>(a);
-  }
+  // add the staged drop table and the tile's colours to the maxima's bytes
+  const int64_t W = (int64_t)a.Cs * a.nb;
+  const int64_t R = std::max<int64_t>(1, (4 * 8 * BLOCK) / W);
+  const size_t total = (lds ? (lds + 15) / 16 * 16 : 0) + (a.kc ? ((size_t)a.kc * a.Cs * 2 + 15) / 16 * 16 : 0) +
+                       ((size_t)R * a.nb + 15) / 16 * 16;
+  auto go = [&](auto kern) {
+    if (total > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total);
+    kern<<<grid, BLOCK, total, s>>>(a);
+  };
+  if (dtype == DT_F32) go(k_ema_single<float, true>);
+  else if (dtype == DT_F64) go(k_ema_single<double, false>);
+  else go(k_ema_single<uint64_t, false>);
 }
 
 void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) {

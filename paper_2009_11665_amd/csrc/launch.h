@@ -122,6 +122,8 @@ struct EmaArgs {
   int *ovf;
   int32_t accumulate;    // general kernel: 1 adds into Ms (adjoint)
   int32_t nb;            // single-vertex kernel: colourings in the pass (columns j * Cs + C)
+  int32_t kc;            // single-vertex kernel: colours, when the drop table is staged in
+                         // LDS as uint16 (indices below 0xFFFF), else 0
 };
 
 // colour-restricted multiply-add (rows bucketed by colour)
@@ -207,7 +209,8 @@ void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const in
 int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
                        hipStream_t s);
 // grid.y must be 1 (the kernel covers a.nb colourings); lds = nb * Cs * 4
-// when FP32S column maxima are tracked (a.mx non-null), else 0
+// when FP32S column maxima are tracked (a.mx non-null), else 0 (the launcher
+// adds the staged drop table and colours)
 void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipStream_t s);
 void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s);
 // block per vertex row, rows staged in LDS; lds = bytes of the staged rows

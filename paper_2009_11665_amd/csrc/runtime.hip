@@ -1216,6 +1216,8 @@ sg2v_status step_ema(Ctx &x, int node, bool single) {
   const size_t lmx = (sc && !wide && !single) ? lmx_cols * 4 : 0;
   if (single) {
     a.nb = x.b;
+    // the drop table in LDS while it leaves room for several blocks per CU
+    if ((int64_t)P.k * nd.cols * 2 <= 16 * 1024 && Bt.cols < 0xFFFF) a.kc = P.k;
     const int64_t rows = std::max<int64_t>(1, 8192 / ((int64_t)nd.cols * x.b));
     const int64_t tiles = (x.g->n + rows - 1) / rows;
     dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)x.cu_count * 8)), 1);
