@@ -2193,7 +2193,7 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
   ST_TRY(sg2v_color(g, plan->p.k, 0x5EEDULL, 0, n_colorings, stream, &c));
   std::unique_ptr<sg2v_colorings> hold(c);
   std::vector<sg2v_tuning_t> cand;
-  const int widths[] = {16, 32, 64};
+  const int widths[] = {16, 32, 64, 128};
   const int rows[] = {4, 8, 16};
   const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_SPMM_UNROLL8 | SG2V_TUNE_XSPLIT;
   for (int w : widths)
