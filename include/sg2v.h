@@ -209,8 +209,10 @@ sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n_plans,
  * the backward sweep instead of being stored.
  *   grad_colorful : host, n_colorings doubles.
  *   grad_w        : device, nnz doubles, written.
- * mode: SG2V_FP64 (the forward tables and the adjoint run in FP64; other
- * modes are rejected with EINVAL).  Errors: EINVAL, ENOMEM, EDEVICE. */
+ * mode: SG2V_FP64, or SG2V_FP32S (FP32 tables, forward and adjoint, each
+ * adjoint table with a power-of-two exponent per colouring; the per-entry
+ * gradient accumulates in FP64).  U64 is rejected with EINVAL.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
 sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
                             sg2v_mode mode, const double *grad_colorful, void *grad_w,
                             void *stream);

@@ -323,7 +323,7 @@ def count_grad(plan: Plan, graph: Graph, col: Colorings, grad_colorful, mode="fp
     import torch
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     gc = np.ascontiguousarray(grad_colorful, np.float64)
-    out = torch.empty(graph.nnz, dtype=torch.float64, device="cuda")  # FP64 only (else EINVAL)
+    out = torch.empty(graph.nnz, dtype=torch.float64, device="cuda")  # FP64 in both modes
     _check(lib().sg2v_count_grad(plan.h, graph.h, col.h, m, _ptr(gc), _ptr(out), _stream(stream)),
            "sg2v_count_grad")
     return out

@@ -1466,15 +1466,30 @@ __global__ void __launch_bounds__(BLOCK) k_sddmm(SddmmArgs a) {
         const int64_t j = a.col_idx[e];
         if (M) {
           const T *mrow = M + j * a.ldm;
-          for (int64_t c = sub; c < a.ncols; c += 16) s = A::fma(brow[c], mrow[c], s, ovf);
+          if (a.fm) {  // FP32S: the passive table's column factors
+            for (int64_t c = sub; c < a.ncols; c += 16) s = A::fma(brow[c], mrow[c] * (T)a.fm[c], s, ovf);
+          } else {
+            for (int64_t c = sub; c < a.ncols; c += 16) s = A::fma(brow[c], mrow[c], s, ovf);
+          }
         } else {
           for (int jj = sub; jj < a.b; jj += 16)
             s = A::add(s, brow[(int64_t)jj * a.k + a.colors[(int64_t)(a.j0 + jj) * a.n + j]], ovf);
         }
       }
       for (int off = 1; off < 16; off <<= 1) s = A::add(s, shfl_xor(s, off), ovf);
-      if (e < end && sub == 0) a.grad[e] += (double)s;
+      if (e < end && sub == 0) a.grad[e] += a.scale * (double)s;
     }
+  }
+}
+
+// Y = Y * so + X * sn over n rows of `cols` columns (FP32S adjoint: a
+// contribution added to a table after both are brought to a common exponent)
+__global__ void k_scale_add(float *Y, int64_t ldy, const float *X, int64_t ldx, int64_t n, int64_t cols,
+                            float so, float sn) {
+  const int64_t total = n * cols;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q / cols, c = q - i * cols;
+    Y[i * ldy + c] = Y[i * ldy + c] * so + X[i * ldx + c] * sn;
   }
 }
 
@@ -1751,6 +1766,12 @@ void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
 void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_copy_i32<<<grid_cap((n + BLOCK - 1) / BLOCK, 4096), BLOCK, 0, s>>>(src, dst, n);
+}
+
+void launch_scale_add(float *Y, int64_t ldy, const float *X, int64_t ldx, int64_t n, int64_t cols, float so,
+                      float sn, hipStream_t s) {
+  if (n == 0 || cols == 0) return;
+  k_scale_add<<<grid_cap((n * cols + BLOCK - 1) / BLOCK, 65536), BLOCK, 0, s>>>(Y, ldy, X, ldx, n, cols, so, sn);
 }
 
 void launch_sddmm(int dtype, const SddmmArgs &a, hipStream_t s) {

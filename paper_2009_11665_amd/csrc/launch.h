@@ -172,6 +172,8 @@ struct SddmmArgs {
   const uint8_t *colors;
   int32_t j0, b, k;
   double *grad;
+  const float *fm;  // nullable: FP32S column factors of Mp
+  double scale;     // grad[e] += scale * (per-entry sum)
 };
 
 struct RootArgs {
@@ -234,6 +236,9 @@ void launch_root_exp(const int *EX, const int *EY, int *out, int b, hipStream_t 
 void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s);
 void launch_sddmm(int dtype, const SddmmArgs &a, hipStream_t s);
+// Y = Y * so + X * sn, n rows of cols columns
+void launch_scale_add(float *Y, int64_t ldy, const float *X, int64_t ldx, int64_t n, int64_t cols, float so,
+                      float sn, hipStream_t s);
 void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t s);
 // FP32S: mx[j * Cs + C] = an upper bound of the column maxima of a
 // single-vertex-active output from the passive table's maxima and factors

@@ -1819,13 +1819,274 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
 //   Mbar_p += A_G Bbar                       (A_G symmetric)
 // The forward tables M_a, M_p and B of each split are recomputed by a forward
 // pass that stops before the split, not stored.
+// FP32S adjoint: the sweep of the FP64 adjoint below with FP32 tables.  Each
+// adjoint table holds FP32 mantissas and one power-of-two exponent per
+// colouring, kept on the host (INT_MIN: the table is zero).  Before an
+// adjoint table is multiplied, its maximum is brought below 1 by an exact
+// power of two; a contribution to a table that already holds values is added
+// after both are brought to the larger exponent (k_scale_add).  The forward
+// tables are recomputed in FP32S and their frame exponents read back; the
+// per-entry gradient accumulates in FP64.
+sg2v_status count_grad_fp32s(const sg2v_plan *plan, sg2v_graph *gg, const sg2v_colorings *c,
+                             const double *grad_colorful, double *grad_w, hipStream_t s) {
+  const Plan &P = plan->p;
+  const sg2v_graph *g = gg;
+  const size_t nn = P.nodes.size();
+  int64_t widest = 1;
+  for (auto &nd : P.nodes)
+    if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? P.k : nd.cols);
+  const int G = pick_G(DT_F32, widest, g->n);
+  const int W = G * 4;
+  const int64_t align = std::max<int64_t>(32, W);
+  std::vector<int64_t> off(nn, -1), ld(nn, 0);
+  int64_t top = 0, bbar_ld = 0, maxld = 1, maxcols = 1;
+  for (size_t q = 0; q < nn; ++q) {
+    const Node &nd = P.nodes[q];
+    if (nd.n_passive_uses > 0) bbar_ld = std::max(bbar_ld, round_up(nd.size == 1 ? P.k : nd.cols, align));
+    maxcols = std::max(maxcols, nd.size == 1 ? (int64_t)P.k : nd.cols);
+    if (nd.size == 1) continue;
+    ld[q] = round_up(nd.cols, align);
+    maxld = std::max(maxld, ld[q]);
+    off[q] = top;
+    top += round_up(g->n * ld[q] * 4, 256);
+  }
+  maxld = std::max(maxld, bbar_ld);
+  const int64_t bbar_off = top;
+  top += round_up(g->n * bbar_ld * 4, 256);
+  const int64_t tmp_off = top;  // contributions before they are added
+  top += round_up(g->n * maxld * 4, 256);
+  const int64_t part_off = top;  // long-row partial rows of the adjoint SpMM
+  top += round_up(std::max<int64_t>(g->n_slots, 1) * maxld * 4, 256);
+  const int64_t small_off = top;  // column maxima, factors, exponents
+  top += round_up(maxcols * 12 + 64, 256);
+  Workspace &ws = workspace();
+  ST_TRY(ws.grad.ensure(top));
+  char *gbase = (char *)ws.grad.p;
+  float *bbar = (float *)(gbase + bbar_off);
+  float *tmp = (float *)(gbase + tmp_off);
+  unsigned *mxb = (unsigned *)(gbase + small_off);
+  float *fq = (float *)(gbase + small_off + maxcols * 4);
+  int *esd = (int *)(gbase + small_off + maxcols * 8);
+  int *zero = esd + maxcols;  // one int, 0: the exponents the FP32S kernels add
+  auto mbar = [&](int q) { return (float *)(gbase + off[q]); };
+  launch_fill_u32((unsigned *)zero, 1, 0u, s);
+
+  // exponent shift d with max(X) * 2^-d < 1, INT_MIN for an all-zero table
+  std::vector<unsigned> hmx((size_t)maxcols);
+  auto shift_of = [&](const float *X, int64_t ldx, int64_t cols, int *d) -> sg2v_status {
+    launch_fill_u32(mxb, cols, 0u, s);
+    launch_colmax(X, g->n, ldx, cols, mxb, s);
+    HIP_TRY(hipMemcpyAsync(hmx.data(), mxb, (size_t)cols * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    unsigned m = 0;
+    for (int64_t q = 0; q < cols; ++q) m = std::max(m, hmx[q]);
+    *d = m == 0 ? INT_MIN : (int)((m >> 23) & 0xFF) - 127 + 1;
+    return SG2V_OK;
+  };
+  auto frame_of = [&](const Tab &t, int *E) -> sg2v_status {
+    HIP_TRY(hipMemcpyAsync(E, t.E, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SG2V_OK;
+  };
+  // table Y (exponent *ey) += X (exponent ex)
+  auto add_to = [&](float *Y, int64_t ldy, int *ey, const float *X, int64_t ldx, int64_t cols, int ex) {
+    if (ex == INT_MIN) return;
+    const int e = *ey == INT_MIN ? ex : std::max(*ey, ex);
+    const float so = *ey == INT_MIN ? 0.f : std::ldexp(1.0f, *ey - e);
+    launch_scale_add(Y, ldy, X, ldx, g->n, cols, so, std::ldexp(1.0f, ex - e), s);
+    *ey = e;
+  };
+
+  std::vector<int> ebar(nn, INT_MIN);
+  for (int j = 0; j < c->count; ++j) {
+    if (grad_colorful[j] == 0.0) continue;
+    launch_fill_value(DT_F32, gbase, bbar_off / 4, 0.0, s);
+    std::fill(ebar.begin(), ebar.end(), INT_MIN);
+    int eg = 0;
+    // seed |g| as mantissa times 2^eg; every adjoint value carries the sign of g
+    const double sg = grad_colorful[j] < 0.0 ? -1.0 : 1.0;
+    const double mg = std::frexp(std::fabs(grad_colorful[j]), &eg);
+    launch_fill_value(DT_F32, mbar(P.root), g->n * ld[P.root], mg, s);
+    ebar[P.root] = eg;
+    for (int q = (int)nn - 1; q >= 0; --q) {
+      const Node &nd = P.nodes[q];
+      if (nd.size == 1 || ebar[q] == INT_MIN) continue;
+      const Node &A = P.nodes[nd.active];
+      const Node &Pn = P.nodes[nd.passive];
+      const int64_t cs = nd.cols, ca = A.size == 1 ? P.k : A.cols;
+      int d = 0;
+      ST_TRY(shift_of(mbar(q), ld[q], cs, &d));
+      if (d == INT_MIN) continue;  // zero adjoint: no contributions
+      const int eq = ebar[q] + d;
+      launch_fill_value(DT_F32, fq, cs, std::ldexp(1.0, -d), s);
+      PassOpts opt;
+      opt.no_fuse = true;
+      if (A.size > 1) opt.keep.push_back({nd.active, 0});
+      if (Pn.size > 1) opt.keep.push_back({nd.passive, 0});
+      opt.keep.push_back({nd.passive, 1});
+      Ctx x;
+      ST_TRY(prepare(x, plan, gg, c, SG2V_FP32S, 1, s, opt));
+      ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
+      x.j0 = j;
+      ST_TRY(run_pass(x, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr, q));
+      Tab &Bp = x.pp.B[nd.passive];
+      const int64_t cp = Bp.cols;
+      int EB = 0, EA = 0, EP = 0;
+      ST_TRY(frame_of(Bp, &EB));
+      if (A.size > 1) ST_TRY(frame_of(x.pp.M[nd.active], &EA));
+      if (Pn.size > 1) ST_TRY(frame_of(x.pp.M[nd.passive], &EP));
+      // Mbar_a += eMA^T over the active index
+      if (A.size > 1) {
+        EmaArgs a{};
+        std::memset(&a, 0, sizeof(a));
+        a.Ma = mbar(q);
+        a.lda = ld[q];
+        a.Ca = (int32_t)cs;
+        a.fa = fq;
+        a.B = Bp.p;
+        a.ldb = Bp.ld;
+        a.Cb = (int32_t)cp;
+        a.fb = Bp.f;
+        a.Ms = tmp;
+        a.lds = ld[nd.active];
+        a.Cs = (int32_t)ca;
+        a.pairs = x.dp.tr_a[q];
+        a.np = nd.np_ta;
+        a.n = g->n;
+        a.ovf = x.ovf;
+        a.Ea = a.Eb = zero;
+        a.es = esd;
+        {
+          ProfScope ps(SG2V_K_EMA_GENERAL, (double)g->n * (cs + cp + ca) * 4, (double)g->n * ca * nd.np_ta, s);
+          ST_TRY(launch_general(x, a));
+        }
+        add_to(mbar(nd.active), ld[nd.active], &ebar[nd.active], tmp, ld[nd.active], ca, eq + EB);
+      }
+      // Bbar over the passive index
+      int ebb = eq;
+      {
+        EmaArgs a{};
+        std::memset(&a, 0, sizeof(a));
+        a.Ms = bbar;
+        a.lds = bbar_ld;
+        a.Cs = (int32_t)cp;
+        a.n = g->n;
+        a.colors = c->d;
+        a.j0 = j;
+        a.ovf = x.ovf;
+        a.es = esd;
+        a.Ea = a.Eb = zero;
+        if (A.size > 1) {
+          Tab &Ma = x.pp.M[nd.active];
+          a.Ma = mbar(q);
+          a.lda = ld[q];
+          a.Ca = (int32_t)cs;
+          a.fa = fq;
+          a.B = Ma.p;
+          a.ldb = Ma.ld;
+          a.Cb = (int32_t)ca;
+          a.fb = Ma.f;
+          a.pairs = x.dp.tr_p[q];
+          a.np = nd.np_tp;
+          ebb = eq + EA;
+          ProfScope ps(SG2V_K_EMA_GENERAL, (double)g->n * (cs + ca + cp) * 4, (double)g->n * cp * nd.np_tp, s);
+          ST_TRY(launch_general(x, a));
+        } else {
+          a.B = mbar(q);
+          a.ldb = ld[q];
+          a.Cb = (int32_t)cs;
+          a.fb = fq;
+          a.drop = x.dp.add[q];
+          a.nb = 1;
+          const int64_t rows = std::max<int64_t>(1, 8192 / cp);
+          dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((g->n + rows - 1) / rows, 2048)), 1);
+          ProfScope ps(SG2V_K_EMA_SINGLE, (double)g->n * (cs + cp) * 4, (double)g->n * cp, s);
+          launch_ema_single(DT_F32, a, grid, 0, s);
+        }
+      }
+      // edge gradient
+      {
+        SddmmArgs dd{};
+        dd.row_ptr = g->row_ptr;
+        dd.col_idx = g->col_idx;
+        dd.Bbar = bbar;
+        dd.ldb = bbar_ld;
+        dd.Mp = Pn.size > 1 ? x.pp.M[nd.passive].p : nullptr;
+        dd.ldm = Pn.size > 1 ? x.pp.M[nd.passive].ld : 0;
+        dd.fm = Pn.size > 1 ? x.pp.M[nd.passive].f : nullptr;
+        dd.scale = sg * std::ldexp(1.0, ebb + (Pn.size > 1 ? EP : 0));
+        dd.ncols = cp;
+        dd.n = g->n;
+        dd.colors = c->d;
+        dd.j0 = j;
+        dd.b = 1;
+        dd.k = P.k;
+        dd.grad = grad_w;
+        ProfScope ps(SG2V_K_SPMM, (double)g->nnz * 12 + (double)g->n * cp * 8, (double)g->nnz * cp, s);
+        launch_sddmm(DT_F32, dd, s);
+      }
+      // Mbar_p += A_G Bbar
+      if (Pn.size > 1) {
+        UnitTable *U = nullptr;
+        ST_TRY(build_units(gg, G, s, &U));
+        SpmmArgs a{};
+        a.col_idx = g->col_idx;
+        a.w = g->w;
+        a.task_row = g->task_row;
+        a.task_beg = g->task_beg;
+        a.task_len = g->task_len;
+        a.task_slot = g->task_slot;
+        a.unit_task = U->unit_task;
+        a.unit_rpw = U->unit_rpw;
+        a.unit_ntask = U->unit_ntask;
+        a.n_units = U->n_units;
+        a.M = bbar;
+        a.ldm = bbar_ld;
+        a.B = tmp;
+        a.ldb = ld[nd.passive];
+        a.partial = gbase + part_off;
+        a.ncols_valid = cp;
+        a.ovf = x.ovf;
+        a.colors = c->d;
+        a.j0 = j;
+        a.n = g->n;
+        a.nnz = g->nnz;
+        const int64_t chunks = (cp + W - 1) / W;
+        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)), (unsigned)chunks);
+        {
+          ProfScope ps(SG2V_K_SPMM, 2.0 * g->n * cp * 4 + (double)chunks * g->nnz * 8, (double)g->nnz * cp, s);
+          if (launch_spmm(DT_F32, a, G, 4, grid, s)) {
+            set_error("sg2v_count_grad: no SpMM variant for G=%d", G);
+            return SG2V_EINVAL;
+          }
+        }
+        CombineArgs cb{};
+        cb.partial = a.partial;
+        cb.B = tmp;
+        cb.ld = a.ldb;
+        cb.ncols_valid = cp;
+        cb.long_row = g->long_row;
+        cb.long_slot0 = g->long_slot0;
+        cb.long_nslot = g->long_nslot;
+        cb.n_long = g->n_long;
+        cb.ovf = x.ovf;
+        launch_spmm_combine(DT_F32, cb, s);
+        add_to(mbar(nd.passive), ld[nd.passive], &ebar[nd.passive], tmp, ld[nd.passive], cp, ebb);
+      }
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return SG2V_OK;
+}
+
 extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *g,
                                        const sg2v_colorings *c, sg2v_mode mode,
                                        const double *grad_colorful, void *grad_w,
                                        void *stream) {
   ST_TRY(check_inputs(plan, g, c, mode));
-  if (mode != SG2V_FP64) {
-    set_error("sg2v_count_grad: only SG2V_FP64 is supported");
+  if (mode != SG2V_FP64 && mode != SG2V_FP32S) {
+    set_error("sg2v_count_grad: mode must be SG2V_FP64 or SG2V_FP32S");
     return SG2V_EINVAL;
   }
   if (!grad_colorful || !grad_w) {
@@ -1841,6 +2102,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
     HIP_TRY(hipStreamSynchronize(s));
     return SG2V_OK;
   }
+  if (mode == SG2V_FP32S) return count_grad_fp32s(plan, gg, c, grad_colorful, (double *)grad_w, s);
   const size_t nn = P.nodes.size();
   int64_t widest = 1;
   for (auto &nd : P.nodes)
@@ -1961,6 +2223,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
         d.b = 1;
         d.k = P.k;
         d.grad = (double *)grad_w;
+        d.scale = 1.0;
         ProfScope ps(SG2V_K_SPMM, (double)g->nnz * 12 + (double)g->n * cp * 16,
                      (double)g->nnz * cp, s);
         launch_sddmm(DT_F64, d, s);

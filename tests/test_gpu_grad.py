@@ -155,12 +155,65 @@ def test_autograd_function():
     np.testing.assert_allclose(w.grad.double().cpu().numpy(), ref, rtol=1e-6)
 
 
-def test_grad_rejects_modes_other_than_fp64():
+def test_grad_rejects_u64():
     G = gg.tiny_er()
     g = sg.Graph.from_csr(G)
     p = sg.Plan(gg.PATH5, 5)
     c = sg.Colorings(g, 5, 1, 1)
-    for mode in ("fp32s", "u64"):
-        with pytest.raises(sg.Sg2vError) as e:
-            sg.count_grad(p, g, c, [1.0], mode)
-        assert e.value.status == -1
+    with pytest.raises(sg.Sg2vError) as e:
+        sg.count_grad(p, g, c, [1.0], "u64")
+    assert e.value.status == -1
+
+
+def _fp32s_vs(go, gw32, rtol=2e-5):
+    """FP32S gradient against a reference: relative per entry, with an
+    absolute floor of rtol times the largest entry (FP32 frame scaling keeps
+    relative accuracy for entries near the table maxima)."""
+    np.testing.assert_allclose(gw32, go, rtol=rtol, atol=rtol * np.abs(go).max())
+
+
+def test_grad_fp32s_small_graphs_vs_oracle():
+    rng = np.random.default_rng(7)
+    for trial in range(6):
+        n = int(rng.integers(20, 60))
+        edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < 0.15]
+        G = gg.from_edge_list(n, edges, rng.uniform(0.5, 1.5, len(edges)))
+        t = int(rng.integers(2, 8))
+        par = random_tree(t, rng)
+        say("grad fp32s small", trial, par)
+        g = sg.Graph(G.n, G.row_ptr, G.col_idx, G.w)
+        c = sg.Colorings(g, t, 3, 1)
+        gw = sg.count_grad(sg.Plan(par, t), g, c, [1.0], "fp32s").cpu().numpy()
+        _, go = O.grad(G, par, t, O.colors(G.n, t, 3, 0))
+        _fp32s_vs(go, gw)
+
+
+def test_grad_fp32s_colourings_and_signs():
+    """FP32S adjoint over three colourings weighted 0.5, -2, 1.25 (the sign
+    of a colouring's weight carries through its scaled tables)."""
+    G = gg.chung_lu(3000, 8.0, 2.1, seed=11, weighted=True)
+    par, k = gg.CATERPILLAR10, 10
+    gc = [0.5, -2.0, 1.25]
+    g = sg.Graph(G.n, G.row_ptr, G.col_idx, G.w)
+    c = sg.Colorings(g, k, 9, 3)
+    gw = sg.count_grad(sg.Plan(par, k), g, c, gc, "fp32s").cpu().numpy()
+    ref = np.zeros(G.nnz)
+    for j, a in enumerate(gc):
+        _, go = O.grad(G, par, k, O.colors(G.n, k, 9, j))
+        ref += a * go
+    _fp32s_vs(ref, gw)
+
+
+@pytest.mark.parametrize("par,k", [(gg.BINTREE7, 7), (gg.PATH8, 8), (gg.CATERPILLAR10, 11)])
+def test_grad_fp32s_matches_fp64_on_rmat(par, k):
+    """RMAT scale 14 with 800,000 entries (a row of 5228 neighbours is split
+    over tasks), unweighted: the FP32S adjoint against the FP64 adjoint of the
+    same colouring."""
+    G = gg.rmat(14, 400_000, seed=17)
+    g = sg.Graph.from_csr(G)
+    c = sg.Colorings(g, k, 2, 1)
+    p = sg.Plan(par, k)
+    say("grad fp32s rmat14", par, k)
+    g64 = sg.count_grad(p, g, c, [1.0], "fp64").cpu().numpy()
+    g32 = sg.count_grad(p, g, c, [1.0], "fp32s").cpu().numpy()
+    _fp32s_vs(g64, g32)
