@@ -207,11 +207,26 @@ def adjoint_workload(sg, gg, torch, reps=2):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(reps):
-        sg.count_grad(p, g, c, [1.0], "fp64")
+        g64 = sg.count_grad(p, g, c, [1.0], "fp64")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    return {"workload": "chung-lu n=262144 d=16 gamma=2.1 weighted; caterpillar10 k=10; 1 colouring, fp64",
+    sg.count(p, g, c, "fp32s")
+    sg.count_grad(p, g, c, [1.0], "fp32s")
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(reps):
+        sg.count(p, g, c, "fp32s")
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(reps):
+        g32 = sg.count_grad(p, g, c, [1.0], "fp32s")
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    d = (g32 - g64).abs()
+    return {"workload": "chung-lu n=262144 d=16 gamma=2.1 weighted; caterpillar10 k=10; 1 colouring",
             "ms_forward": (t1 - t0) / reps * 1e3, "ms_adjoint": (t2 - t1) / reps * 1e3,
+            "ms_forward_fp32s": (t4 - t3) / reps * 1e3, "ms_adjoint_fp32s": (t5 - t4) / reps * 1e3,
+            "fp32s_vs_fp64_grad_max_abs_err_over_max": float(d.max() / g64.abs().max()),
             "entries": G.nnz}
 
 

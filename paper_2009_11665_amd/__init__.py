@@ -367,39 +367,40 @@ def profile_stop():
 
 class SubgraphCount:
     """Differentiable colourful count: ``SubgraphCount.apply(w, plan, row_ptr,
-    col_idx, seed, n_colorings)`` returns the colourful count of each colouring
-    (float64 [n_colorings]) of the graph whose CSR entries carry the weights
-    ``w`` (device tensor [nnz]); its backward gives d/dw per directed entry via
-    sg2v_count_grad (FP64).  The forward runs in FP64 as well."""
+    col_idx, seed, n_colorings, mode="fp64")`` returns the colourful count of
+    each colouring (float64 [n_colorings]) of the graph whose CSR entries carry
+    the weights ``w`` (device tensor [nnz]); its backward gives d/dw per
+    directed entry via sg2v_count_grad.  mode "fp64" or "fp32s" applies to the
+    forward and the adjoint."""
 
     _fn = None
 
     @classmethod
-    def apply(cls, w, plan, row_ptr, col_idx, seed, n_colorings):
+    def apply(cls, w, plan, row_ptr, col_idx, seed, n_colorings, mode="fp64"):
         if cls._fn is None:
             import torch
 
             class _F(torch.autograd.Function):
                 @staticmethod
-                def forward(ctx, w, plan, row_ptr, col_idx, seed, n_colorings):
+                def forward(ctx, w, plan, row_ptr, col_idx, seed, n_colorings, mode):
                     n = row_ptr.numel() - 1
                     g = Graph(n, row_ptr, col_idx, w.detach())
                     c = Colorings(g, plan.k, seed, n_colorings)
-                    r = count(plan, g, c, "fp64")
-                    ctx.keep = (g, c, plan)
+                    r = count(plan, g, c, mode)
+                    ctx.keep = (g, c, plan, mode)
                     return torch.as_tensor(r["colorful"], dtype=torch.float64, device=w.device)
 
                 @staticmethod
                 def backward(ctx, grad_out):
-                    g, c, plan = ctx.keep
-                    gw = count_grad(plan, g, c, grad_out.detach().double().cpu().numpy(), "fp64")
-                    return gw.to(w_dtype(ctx)), None, None, None, None, None
+                    g, c, plan, mode = ctx.keep
+                    gw = count_grad(plan, g, c, grad_out.detach().double().cpu().numpy(), mode)
+                    return gw.to(w_dtype(ctx)), None, None, None, None, None, None
 
             def w_dtype(ctx):
                 return ctx.keep[0]._keep[2].dtype
 
             cls._fn = _F
-        return cls._fn.apply(w, plan, row_ptr, col_idx, seed, n_colorings)
+        return cls._fn.apply(w, plan, row_ptr, col_idx, seed, n_colorings, mode)
 
 
 def autotune(plan: Plan, graph: Graph, mode="fp32s", n_colorings: int = 1, stream=None) -> Tuning:

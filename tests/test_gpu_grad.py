@@ -139,20 +139,38 @@ def test_grad_diff_config_sampled_vs_oracle_and_fd():
         assert fd == pytest.approx(gu[e], rel=1e-6, abs=1e-9 * abs(f[0]))
 
 
-def test_autograd_function():
+@pytest.mark.parametrize("mode", ["fp64", "fp32s"])
+def test_autograd_function(mode):
     import torch
     G = gg.chung_lu(2000, 6.0, 2.1, seed=5, weighted=True)
     par, k = gg.PATH5, 5
     rp = torch.as_tensor(G.row_ptr, device="cuda")
     ci = torch.as_tensor(G.col_idx, device="cuda")
     w = torch.as_tensor(G.w, device="cuda").requires_grad_(True)
-    out = sg.SubgraphCount.apply(w, sg.Plan(par, k), rp, ci, 8, 2)
+    out = sg.SubgraphCount.apply(w, sg.Plan(par, k), rp, ci, 8, 2, mode)
     (out * torch.tensor([1.0, 3.0], dtype=torch.float64, device="cuda")).sum().backward()
     ref = np.zeros(G.nnz)
     for j, a in enumerate((1.0, 3.0)):
         _, go = O.grad(G, par, k, O.colors(G.n, k, 8, j))
         ref += a * go
-    np.testing.assert_allclose(w.grad.double().cpu().numpy(), ref, rtol=1e-6)
+    # w is float32: the gradient is returned in w's dtype
+    np.testing.assert_allclose(w.grad.double().cpu().numpy(), ref, rtol=1e-6 if mode == "fp64" else 2e-5,
+                               atol=0 if mode == "fp64" else 2e-5 * np.abs(ref).max())
+
+
+def test_grad_fp32s_diff_config_sampled_vs_oracle():
+    """The differentiation workload (Chung-Lu n=262,144, mean degree 16,
+    weights U[0.5,1.5), caterpillar10) in FP32S: 256 sampled entries against
+    the oracle's reverse mode."""
+    G = gg.chung_lu_262k_weighted()
+    par, k, seed = gg.CATERPILLAR10, 10, 3
+    g = sg.Graph(G.n, G.row_ptr, G.col_idx, G.w)
+    c = sg.Colorings(g, k, seed, 1)
+    gw = sg.count_grad(sg.Plan(par, k), g, c, [1.0], "fp32s").cpu().numpy()
+    _, go = O.grad(G, par, k, O.colors(G.n, k, seed, 0))
+    sample = np.random.default_rng(1).choice(G.nnz, 256, replace=False)
+    say("diff config fp32s")
+    np.testing.assert_allclose(gw[sample], go[sample], rtol=2e-5, atol=2e-5 * np.abs(go).max())
 
 
 def test_grad_rejects_u64():
