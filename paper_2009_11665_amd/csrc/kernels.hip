@@ -46,14 +46,13 @@ void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t fir
 //   H(i, jj*k + c) = sum_{e in row i} w_e [colour_jj(col_idx[e]) == c].
 // One wave per SpMM task (a row, or a segment of at most 4096 neighbours of
 // a long row whose partial row goes to its slot and is summed by
-// k_spmm_combine); lanes over neighbours, four blocks of 64 neighbours in
-// flight; lane c keeps colour c's sum.  Unweighted counts use a ballot per
-// colour, weighted sums a fixed-order butterfly, so the result does not
-// depend on scheduling.
+// k_spmm_combine); lanes over neighbours, D blocks of 64 neighbours and JG
+// colourings of the pass in flight; lane c keeps colour c's sum.  Unweighted
+// counts use a ballot per colour, weighted sums a fixed-order butterfly, so
+// the result does not depend on scheduling.
 
-template <typename T, bool WEIGHTED>
+template <typename T, bool WEIGHTED, int D, int JG>
 __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
-  constexpr int D = 4;
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
   const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
@@ -64,11 +63,14 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
     const int len = a.task_len[t];
     const int slot = a.task_slot[t];
     T *dst = slot < 0 ? H + (int64_t)a.task_row[t] * a.ldh : Pt + (int64_t)slot * a.ldh;
-    for (int jj = 0; jj < a.b; ++jj) {
-      const uint8_t *col = a.colors + (int64_t)(a.j0 + jj) * a.n;
-      T acc = T(0);
+    // colourings JG at a time: the neighbour indices are loaded once per group
+    // and the group's colour gathers are in flight together
+    for (int jg = 0; jg < a.b; jg += JG) {
+      T acc[JG];
+#pragma unroll
+      for (int u = 0; u < JG; ++u) acc[u] = T(0);
       for (int base = 0; base < len; base += D * WAVE) {
-        int j[D], c[D];
+        int j[D], c[D][JG];
         float wv[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) {
@@ -78,23 +80,34 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
           if constexpr (WEIGHTED) wv[q] = e < len ? a.w[beg + e] : 0.0f;
         }
 #pragma unroll
-        for (int q = 0; q < D; ++q) c[q] = j[q] >= 0 ? (int)col[j[q]] : 255;
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+          for (int u = 0; u < JG; ++u)
+            c[q][u] = (j[q] >= 0 && jg + u < a.b) ? (int)a.colors[(int64_t)(a.j0 + jg + u) * a.n + j[q]] : 255;
 #pragma unroll
         for (int q = 0; q < D; ++q) {
           if (base + q * WAVE >= len) break;  // uniform
-          for (int cc = 0; cc < a.k; ++cc) {
-            if constexpr (!WEIGHTED) {
-              const uint64_t m = __ballot(c[q] == cc);
-              if (lane == cc) acc += (T)__popcll(m);
-            } else {
-              T v = (c[q] == cc) ? (T)wv[q] : T(0);
-              for (int off = 1; off < WAVE; off <<= 1) v += shfl_xor(v, off);
-              if (lane == cc) acc += v;
+#pragma unroll
+          for (int u = 0; u < JG; ++u) {
+            if (jg + u >= a.b) break;  // uniform
+            for (int cc = 0; cc < a.k; ++cc) {
+              if constexpr (!WEIGHTED) {
+                const uint64_t m = __ballot(c[q][u] == cc);
+                if (lane == cc) acc[u] += (T)__popcll(m);
+              } else {
+                T v = (c[q][u] == cc) ? (T)wv[q] : T(0);
+                for (int off = 1; off < WAVE; off <<= 1) v += shfl_xor(v, off);
+                if (lane == cc) acc[u] += v;
+              }
             }
           }
         }
       }
-      if (lane < a.k) dst[(int64_t)jj * a.k + lane] = acc;
+      if (lane < a.k) {
+#pragma unroll
+        for (int u = 0; u < JG; ++u)
+          if (jg + u < a.b) dst[(int64_t)(jg + u) * a.k + lane] = acc[u];
+      }
     }
     // partial rows are summed over the whole padded width: clear the padding
     if (slot >= 0)
@@ -1510,8 +1523,15 @@ static inline unsigned grid_cap(int64_t want, int64_t cap) {
 
 template <typename T>
 static void hist_dispatch(const HistArgs &a, int blocks, hipStream_t s) {
-  if (a.w) k_hist<T, true><<<blocks, BLOCK, 0, s>>>(a);
-  else k_hist<T, false><<<blocks, BLOCK, 0, s>>>(a);
+  // one colouring: four neighbour blocks in flight; more: two blocks of four
+  // colourings each
+  if (a.b == 1) {
+    if (a.w) k_hist<T, true, 4, 1><<<blocks, BLOCK, 0, s>>>(a);
+    else k_hist<T, false, 4, 1><<<blocks, BLOCK, 0, s>>>(a);
+  } else {
+    if (a.w) k_hist<T, true, 2, 4><<<blocks, BLOCK, 0, s>>>(a);
+    else k_hist<T, false, 2, 4><<<blocks, BLOCK, 0, s>>>(a);
+  }
 }
 
 void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s) {
