@@ -162,7 +162,7 @@ def batch_workload(sg, gg, torch, reps=3):
         return (time.perf_counter() - t0) / reps, cf
 
     try:
-        tuned = sg.autotune(plans[2], g, "fp32s", 2)
+        tuned = sg.autotune(plans[2], g, "fp32s", ncol)  # probe with the workload's colourings per template
         t_given, cf_given = graph_ms([sg.Plan(p) for p in given])
         t_graph, cf = graph_ms(plans)
         for p, par in zip(plans, pars):  # warm
