@@ -235,3 +235,22 @@ def test_grad_fp32s_matches_fp64_on_rmat(par, k):
     g64 = sg.count_grad(p, g, c, [1.0], "fp64").cpu().numpy()
     g32 = sg.count_grad(p, g, c, [1.0], "fp32s").cpu().numpy()
     _fp32s_vs(g64, g32)
+
+
+@pytest.mark.parametrize("par,k", [([-1, 0], 2), ([-1, 0, 0, 0], 4), (gg.PATH5, 7), ([-1, 0, 1, 1, 0, 4], 8)])
+def test_grad_fp32s_shapes(par, k):
+    """FP32S adjoint on an edge, a star (one-vertex passives only), k > t,
+    and a small tree with k > t, against the oracle's reverse mode."""
+    rng = np.random.default_rng(len(par) * 10 + k)
+    n = 50
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < 0.2]
+    G = gg.from_edge_list(n, edges, rng.uniform(0.5, 1.5, len(edges)))
+    g = sg.Graph(G.n, G.row_ptr, G.col_idx, G.w)
+    c = sg.Colorings(g, k, 5, 2)
+    say("grad fp32s shape", par, k)
+    gw = sg.count_grad(sg.Plan(par, k), g, c, [1.0, 0.25], "fp32s").cpu().numpy()
+    ref = np.zeros(G.nnz)
+    for j, a in enumerate((1.0, 0.25)):
+        _, go = O.grad(G, par, k, O.colors(G.n, k, 5, j))
+        ref += a * go
+    _fp32s_vs(ref, gw)

@@ -280,6 +280,25 @@ def test_edge_cases():
         assert [int(x) for x in r["colorful_u64"]] == [x[1] for x in ref]
 
 
+def test_budget_too_small_is_enomem():
+    """A device-memory budget below one colouring's tables fails with ENOMEM
+    before any kernel runs; the next count with the budget lifted works."""
+    G = gg.tiny_er()
+    g = sg.Graph.from_csr(G)
+    p = sg.Plan(gg.CATERPILLAR10, 10)
+    c = sg.Colorings(g, 10, 1, 1)
+    old = sg.get_tuning()
+    try:
+        sg.set_tuning(budget_bytes=4096)
+        with pytest.raises(sg.Sg2vError) as e:
+            sg.count(p, g, c, "fp32s")
+        assert e.value.status == -4
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+    r = sg.count(p, g, c, "u64")
+    assert int(r["colorful_u64"][0]) == O.count(G, gg.CATERPILLAR10, 10, O.colors(G.n, 10, 1, 0), mode=O.U64)[1]
+
+
 @pytest.mark.parametrize("flags", [0, 16])
 def test_long_rows_split_across_tasks(flags):
     """Rows longer than one SpMM task are split and their partial rows summed
