@@ -141,9 +141,10 @@ def batch_workload(sg, gg, torch, reps=3):
     x 16 colourings on Chung-Lu n = 500,000, mean degree 20, each template
     re-rooted by sg2v_template_reroot (same counts, cheaper decomposition):
     all passes of all templates recorded as one HIP graph (sg2v_count_batch,
-    replayed), against the same counts run template by template, colouring
-    included, and against the templates rooted as given.  Tuning from the
-    autotuner on the widest template."""
+    replayed; the templates are parallel branches of the graph), against the
+    graph with the templates in sequence, the same counts run template by
+    template, colouring included, and the templates rooted as given.  Tuning
+    from the autotuner on the widest template."""
     G = gg.chung_lu_500k()
     g = sg.Graph.from_csr(G)
     given = (gg.BINTREE7, gg.PATH8, gg.CATERPILLAR10)
@@ -165,6 +166,10 @@ def batch_workload(sg, gg, torch, reps=3):
         tuned = sg.autotune(plans[2], g, "fp32s", ncol)  # probe with the workload's colourings per template
         t_given, cf_given = graph_ms([sg.Plan(p) for p in given])
         t_graph, cf = graph_ms(plans)
+        cur = sg.get_tuning()
+        sg.set_tuning(cur.spmm_width, cur.ema_rows, cur.batch, cur.budget_bytes, cur.flags | sg.TUNE_BATCH_SERIAL)
+        t_serial, _ = graph_ms(plans)
+        sg.set_tuning(cur.spmm_width, cur.ema_rows, cur.batch, cur.budget_bytes, cur.flags)
         for p, par in zip(plans, pars):  # warm
             sg.count(p, g, sg.Colorings(g, len(par), seed, ncol), "fp32s")
         torch.cuda.synchronize()
@@ -180,6 +185,7 @@ def batch_workload(sg, gg, torch, reps=3):
         "workload": "chung-lu n=500000 d=20 gamma=2.1; bintree7, path8, caterpillar10 (k=t, re-rooted) x 16 colourings, fp32s",
         "template_colorings_per_s": 3 * ncol / t_graph,
         "ms_one_graph_launch": t_graph * 1e3,
+        "ms_one_graph_launch_templates_in_sequence": t_serial * 1e3,
         "ms_template_by_template": t_seq * 1e3,
         "ms_one_graph_launch_given_roots": t_given * 1e3,
         "rerooted_vs_given_max_rel_diff": float(max(abs(a - b) / abs(b) for a, b in zip(cf.ravel(), cf_given.ravel()))),

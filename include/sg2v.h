@@ -280,6 +280,8 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
                                     get 256-byte chunks in any case) */
 #define SG2V_TUNE_ROOT_ROWS 64   /* root reduction one vertex per block step in vertex order instead
                                     of colour by colour with double-buffered rows */
+#define SG2V_TUNE_BATCH_SERIAL 512 /* sg2v_count_batch: templates one after another in one workspace
+                                      instead of parallel graph branches with a workspace each */
 #define SG2V_TUNE_ROOT_THREAD 256 /* narrow root tables read by one thread per vertex from global
                                      memory instead of staged in LDS a tile of rows at a time */
 typedef struct {

@@ -338,6 +338,7 @@ TUNE_FORCE_XSPLIT = 16
 TUNE_XSPLIT = 32
 TUNE_ROOT_ROWS = 64
 TUNE_ROOT_THREAD = 256
+TUNE_BATCH_SERIAL = 512
 
 
 def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,

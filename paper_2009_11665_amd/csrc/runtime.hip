@@ -1446,7 +1446,7 @@ int choose_batch(const Plan &P, int ncol, int dt, int64_t n, int64_t n_slots) {
 }
 
 sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_colorings *c,
-                    sg2v_mode mode, int b, hipStream_t s, const PassOpts &opt) {
+                    sg2v_mode mode, int b, hipStream_t s, const PassOpts &opt, Workspace *wsp = nullptr) {
   x.P = &plan->p;
   x.g = g;
   x.c = c;
@@ -1454,7 +1454,7 @@ sg2v_status prepare(Ctx &x, const sg2v_plan *plan, sg2v_graph *g, const sg2v_col
   x.es = esize_of(x.dt);
   x.b = b;
   x.s = s;
-  x.ws = &workspace();
+  x.ws = wsp ? wsp : &workspace();
   {
     static std::mutex mu;
     static std::map<int, std::pair<int, size_t>> props;
@@ -1654,6 +1654,9 @@ struct BatchGraph {
   sg2v_tuning_t tune{};
   uint64_t gens[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<std::unique_ptr<sg2v_colorings>> cols;
+  // per-template workspaces when the templates run as parallel graph branches
+  std::vector<std::unique_ptr<Workspace>> wss;
+  bool conc = false;
   hipGraphExec_t exec = nullptr;
   int device = -1;
   ~BatchGraph() {
@@ -1716,43 +1719,83 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
 
-  // colourings and contexts (all uploads and allocations happen here)
-  std::unique_ptr<BatchGraph> bg(new BatchGraph());
-  bg->plans.assign(plans, plans + n_plans);
-  bg->g = g;
-  bg->seed = seed;
-  bg->ncol = ncol;
-  bg->mode = mode;
-  bg->tune = tuning();
-  bg->device = dev;
-  std::vector<Ctx> xs(n_plans);
   std::vector<int> bs(n_plans);
-  for (int p = 0; p < n_plans; ++p) {
-    std::unique_ptr<sg2v_colorings> c(new sg2v_colorings());
-    c->device = dev;
-    c->n = g->n;
-    c->k = plans[p]->p.k;
-    c->count = ncol;
-    c->seed = seed;
-    HIP_TRY(hipMalloc((void **)&c->d, g->n * ncol));
-    bs[p] = choose_batch(plans[p]->p, ncol, dt, g->n, g->n_slots);
-    ST_TRY(prepare(xs[p], plans[p], (sg2v_graph *)g, c.get(), mode, bs[p], us, PassOpts()));
-    ST_TRY(prewarm(xs[p], bs[p]));
-    ST_TRY(prewarm(xs[p], ncol % bs[p]));
-    bg->cols.push_back(std::move(c));
+  for (int p = 0; p < n_plans; ++p) bs[p] = choose_batch(plans[p]->p, ncol, dt, g->n, g->n_slots);
+  // Templates run as parallel branches of the graph, each with a workspace of
+  // its own, when those fit in half of the free device memory (estimated from
+  // the pass plan of each); otherwise one after another in the shared one.
+  const sg2v_tuning_t tune = tuning();
+  bool conc = n_plans > 1 && !(tune.flags & SG2V_TUNE_BATCH_SERIAL);
+  if (conc) {
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    double need = 0;
+    for (int p = 0; p < n_plans; ++p) {
+      PassPlan pp;
+      int64_t widest = 1;
+      for (auto &nd : plans[p]->p.nodes)
+        if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? plans[p]->p.k : nd.cols);
+      build_pass(plans[p]->p, g->n, bs[p], dt, pick_G(dt, widest * bs[p], g->n), g->n_slots, pp, PassOpts());
+      need += (double)pp.arena + pp.small_bytes + (double)bs[p] * (g->nnz + 4.0 * g->n + 64.0);
+    }
+    conc = need <= 0.5 * (double)fr;
   }
+  ST_TRY(ws.ovf.ensure(256));
   ST_TRY(ws.result.ensure((size_t)n_plans * ncol * 12 + 64));
-  HIP_TRY(hipStreamSynchronize(us));
-
-  // reuse a cached executable graph if every input and buffer is unchanged
+  const std::vector<const sg2v_plan *> pv(plans, plans + n_plans);
+  auto same_key = [&](const BatchGraph &e) {
+    return e.g == g && e.seed == seed && e.ncol == ncol && e.mode == mode && e.device == dev && e.plans == pv &&
+           same_tuning(e.tune, tune) && e.conc == conc;
+  };
   uint64_t gens[9];
   ws_gens(ws, gens);
   BatchGraph *hit = nullptr;
-  for (auto &e : g_batch_cache) {
-    if (e->g == g && e->seed == seed && e->ncol == ncol && e->mode == mode && e->device == dev &&
-        e->plans == bg->plans && same_tuning(e->tune, bg->tune) &&
-        std::equal(gens, gens + 9, e->gens))
-      hit = e.get();
+  if (conc) {
+    // a cached graph with workspaces of its own only needs the shared result
+    // and flag buffers unchanged
+    for (auto &e : g_batch_cache)
+      if (same_key(*e) && e->gens[3] == gens[3] && e->gens[4] == gens[4]) hit = e.get();
+  }
+  std::unique_ptr<BatchGraph> bg;
+  std::vector<Ctx> xs(n_plans);
+  if (!hit) {
+    // colourings and contexts (all uploads and allocations happen here)
+    bg.reset(new BatchGraph());
+    bg->plans = pv;
+    bg->g = g;
+    bg->seed = seed;
+    bg->ncol = ncol;
+    bg->mode = mode;
+    bg->tune = tune;
+    bg->device = dev;
+    bg->conc = conc;
+    for (int p = 0; p < n_plans; ++p) {
+      std::unique_ptr<sg2v_colorings> c(new sg2v_colorings());
+      c->device = dev;
+      c->n = g->n;
+      c->k = plans[p]->p.k;
+      c->count = ncol;
+      c->seed = seed;
+      HIP_TRY(hipMalloc((void **)&c->d, g->n * ncol));
+      bg->cols.push_back(std::move(c));
+    }
+    for (int p = 0; p < n_plans; ++p) {
+      Workspace *wp = nullptr;
+      if (conc) {
+        bg->wss.emplace_back(new Workspace());
+        wp = bg->wss.back().get();
+      }
+      ST_TRY(prepare(xs[p], plans[p], (sg2v_graph *)g, bg->cols[p].get(), mode, bs[p], us, PassOpts(), wp));
+      ST_TRY(prewarm(xs[p], bs[p]));
+      ST_TRY(prewarm(xs[p], ncol % bs[p]));
+    }
+    HIP_TRY(hipStreamSynchronize(us));
+    if (!conc) {
+      // reuse a cached executable graph if every input and buffer is unchanged
+      ws_gens(ws, gens);
+      for (auto &e : g_batch_cache)
+        if (same_key(*e) && std::equal(gens, gens + 9, e->gens)) hit = e.get();
+    }
   }
   char *res = (char *)ws.result.p;
   int *Ed = (int *)(res + (size_t)n_plans * ncol * 8);
@@ -1764,17 +1807,36 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
     }
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    // one stream (and one join event) per template for the parallel branches
+    std::vector<hipStream_t> sp(n_plans, cs);
+    std::vector<hipEvent_t> done(n_plans, nullptr);
+    hipEvent_t fork = nullptr;
+    hipError_t he = hipSuccess;
+    if (conc) {
+      he = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+      for (int p = 0; p < n_plans && he == hipSuccess; ++p) {
+        he = hipStreamCreateWithFlags(&sp[p], hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&done[p], hipEventDisableTiming);
+      }
+    }
     hipGraph_t graph = nullptr;
     sg2v_status st = SG2V_OK;
-    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
       t_capturing = true;
       launch_fill_u32((unsigned *)ws.ovf.p, 1, 0u, cs);
-      for (int p = 0; p < n_plans && st == SG2V_OK; ++p) {
-        launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, cs);
-        xs[p].s = cs;
+      if (conc) he = hipEventRecord(fork, cs);
+      for (int p = 0; p < n_plans && st == SG2V_OK && he == hipSuccess; ++p) {
+        if (conc) he = hipStreamWaitEvent(sp[p], fork, 0);
+        if (he != hipSuccess) break;
+        launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, sp[p]);
+        xs[p].s = sp[p];
         xs[p].c = bg->cols[p].get();
         st = enqueue_count(xs[p], ncol, bs[p], res + (size_t)p * ncol * 8, Ed + (size_t)p * ncol);
+        if (conc && st == SG2V_OK) {
+          he = hipEventRecord(done[p], sp[p]);
+          if (he == hipSuccess) he = hipStreamWaitEvent(cs, done[p], 0);
+        }
       }
       t_capturing = false;
       hipError_t he2 = hipStreamEndCapture(cs, &graph);
@@ -1782,6 +1844,13 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
     }
     if (he == hipSuccess && st == SG2V_OK) he = hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
+    if (conc) {
+      for (int p = 0; p < n_plans; ++p) {
+        if (sp[p] && sp[p] != cs) (void)hipStreamDestroy(sp[p]);
+        if (done[p]) (void)hipEventDestroy(done[p]);
+      }
+      if (fork) (void)hipEventDestroy(fork);
+    }
     (void)hipStreamDestroy(cs);
     if (st != SG2V_OK) return st;
     if (he != hipSuccess) {

@@ -20,11 +20,23 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_batch_equals_single_and_oracle():
+@pytest.mark.parametrize("flags", [0, 512])
+def test_batch_equals_single_and_oracle(flags):
+    """flags 0: templates as parallel graph branches with a workspace each;
+    512 (BATCH_SERIAL): one after another in the shared workspace."""
     G = gg.chung_lu(20_000, 12.0, 2.1, seed=4)
     g = sg.Graph.from_csr(G)
     plans = [sg.Plan(p) for p in TEMPLATES]
     seed, ncol = 7, 4
+    old = sg.get_tuning()
+    sg.set_tuning(flags=flags)
+    try:
+        _batch_vs_single(G, g, plans, seed, ncol)
+    finally:
+        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+
+
+def _batch_vs_single(G, g, plans, seed, ncol):
     for mode in ("u64", "fp32s", "fp64"):
         say("batch", mode)
         cf, est = sg.count_batch(plans, g, seed, ncol, mode)
