@@ -193,9 +193,9 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
     }
     const uint64_t gmask = (lpt == 64) ? ~0ull : (((1ull << lpt) - 1ull) << gbase);
     const uint64_t lt = (1ull << lane) - 1ull;
-    V16<T> acc0, acc1, acc2, acc3;
+    V16<T> acc0, acc1;
 #pragma unroll
-    for (int u = 0; u < N; ++u) acc0.x[u] = acc1.x[u] = acc2.x[u] = acc3.x[u] = T(0);
+    for (int u = 0; u < N; ++u) acc0.x[u] = acc1.x[u] = T(0);
 
     // neighbour indices (and colours) of the next block of lpt neighbours are
     // loaded while the current block's rows are gathered
@@ -262,19 +262,15 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
           }
         }
 #pragma unroll
-        for (int q = 0; q < UNR; q += 4) {
+        for (int q = 0; q < UNR; q += 2) {
 #pragma unroll
           for (int u = 0; u < N; ++u) {
             if constexpr (WEIGHTED) {
               acc0.x[u] = A::fma(wq[q + 0], v[q + 0].x[u], acc0.x[u], ovf);
               acc1.x[u] = A::fma(wq[q + 1], v[q + 1].x[u], acc1.x[u], ovf);
-              acc2.x[u] = A::fma(wq[q + 2], v[q + 2].x[u], acc2.x[u], ovf);
-              acc3.x[u] = A::fma(wq[q + 3], v[q + 3].x[u], acc3.x[u], ovf);
             } else {
               acc0.x[u] = A::add(acc0.x[u], v[q + 0].x[u], ovf);
               acc1.x[u] = A::add(acc1.x[u], v[q + 1].x[u], ovf);
-              acc2.x[u] = A::add(acc2.x[u], v[q + 2].x[u], ovf);
-              acc3.x[u] = A::add(acc3.x[u], v[q + 3].x[u], ovf);
             }
           }
         }
@@ -282,7 +278,7 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < N; ++u) {
-      T x = A::add(A::add(acc0.x[u], acc1.x[u], ovf), A::add(acc2.x[u], acc3.x[u], ovf), ovf);
+      T x = A::add(acc0.x[u], acc1.x[u], ovf);
       // butterfly across the task's streams (lanes differing in bits >= log2 G)
       for (int off = G; off < lpt; off <<= 1) x = A::add(x, shfl_xor(x, off), ovf);
       acc0.x[u] = x;
