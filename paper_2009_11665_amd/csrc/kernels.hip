@@ -646,18 +646,18 @@ __global__ void __launch_bounds__(BLOCK) k_bucket_scatter(const uint8_t *colors,
 // Stage the columns idx[0..S) of R rows (row index -1: zeros) into LDS
 // transposed, dst[q * RP + r] (times f[idx[q]] when SCALED), eight loads in
 // flight per thread.
-template <typename T, int R, bool SCALED>
+template <typename T, int R, bool SCALED, int NT>
 __device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t off, const int *rows,
                                   const int32_t *__restrict__ idx, const float *__restrict__ f, int S,
                                   T *__restrict__ dst, int RP) {
   constexpr int U = 8;
   const int total = R * S;
-  for (int x0 = threadIdx.x; x0 < total; x0 += U * BLOCK) {
+  for (int x0 = threadIdx.x; x0 < total; x0 += U * NT) {
     // every load is issued (indices clamped into range) before any is used
     int rr[U], q[U], col[U], row[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int x = min(x0 + u * BLOCK, total - 1);
+      const int x = min(x0 + u * NT, total - 1);
       rr[u] = x / S;
       q[u] = x - rr[u] * S;
       col[u] = idx[q[u]];
@@ -672,7 +672,7 @@ __device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t o
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (x0 + u * BLOCK < total) {
+      if (x0 + u * NT < total) {
         T w = row[u] >= 0 ? v[u] : T(0);
         if constexpr (SCALED) w *= fv[u];
         dst[q[u] * RP + rr[u]] = w;
@@ -688,8 +688,8 @@ __device__ inline void stage_cols(const T *__restrict__ M, int64_t ld, int64_t o
 // columns holding c and the passive columns without c in LDS, and each thread
 // owns output columns (in their natural order, so that whole lines are
 // written): columns holding c from their pairs, the others 0.
-template <typename T, int R, bool SCALED>
-__global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
+template <typename T, int R, bool SCALED, int NT>
+__global__ void __launch_bounds__(NT) k_ema_colour(EmaColourArgs a) {
   using A = Arith<T>;
   constexpr int N = V16<T>::N;
   // staged columns are R rows long, padded by one 16-byte vector so that
@@ -706,7 +706,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   // positive value, else the float's exponent field + 1 (what the frame
   // exponent needs is floor(log2 max), which the code determines exactly)
   uint8_t *lmx = (uint8_t *)(lb + (int64_t)RP * a.Sb);
-  for (int r = threadIdx.x; r < RP; r += BLOCK) la[(int64_t)a.Sa * RP + r] = T(0);
+  for (int r = threadIdx.x; r < RP; r += NT) la[(int64_t)a.Sa * RP + r] = T(0);
   const T *Ma = (const T *)a.Ma;
   const T *Bt = (const T *)a.B;
   T *Ms = (T *)a.Ms;
@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   // column maxima (FP32S) unless the caller measures them afterwards (mx null)
   const bool track = SCALED && a.mx != nullptr;
   if (track)
-    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0;
+    for (int c = threadIdx.x; c < a.Cs; c += NT) lmx[c] = 0;
   int64_t ntiles = 0;
   for (int c = 0; c < a.k; ++c) ntiles += (cnt[c] + R - 1) / R;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -738,14 +738,14 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
     __syncthreads();
     const int32_t *ca = a.ca + (int64_t)c * a.Sa;
     const int32_t *cb = a.cb + (int64_t)c * a.Sb;
-    stage_cols<T, R, SCALED>(Ma, a.lda, (int64_t)j * a.Ca, rows, ca, fa, a.Sa, la, RP);
-    stage_cols<T, R, SCALED>(Bt, a.ldb, (int64_t)j * a.Cb, rows, cb, fb, a.Sb, lb, RP);
+    stage_cols<T, R, SCALED, NT>(Ma, a.lda, (int64_t)j * a.Ca, rows, ca, fa, a.Sa, la, RP);
+    stage_cols<T, R, SCALED, NT>(Bt, a.ldb, (int64_t)j * a.Cb, rows, cb, fb, a.Sb, lb, RP);
     __syncthreads();
     // output columns in their natural order, so that each wave writes whole
     // lines: columns holding c from their pairs, the others zero
     const uint32_t *cp = a.cp + (int64_t)c * a.Q * a.U;
     const int32_t *cu = a.cu + (int64_t)c * a.Cs;
-    for (int C = threadIdx.x; C < a.Cs; C += BLOCK) {
+    for (int C = threadIdx.x; C < a.Cs; C += NT) {
       const int u = cu[C];
       T acc[R];
 #pragma unroll
@@ -791,7 +791,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_colour(EmaColourArgs a) {
   }
   if constexpr (SCALED) {
     __syncthreads();
-    for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
+    for (int c = threadIdx.x; c < a.Cs; c += NT) {
       // a float with the same floor(log2): 2^(field - 127), or the smallest
       // subnormal for a subnormal maximum
       const uint32_t code = track ? lmx[c] : 0u;
@@ -1738,24 +1738,31 @@ void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int3
       colors, n, j0, k, counts, cursor, perm);
 }
 
-template <typename T, bool SC>
-static int ema_colour_t(const EmaColourArgs &a, int R, dim3 grid, size_t lds, hipStream_t s) {
+template <typename T, bool SC, int NT>
+static int ema_colour_nt(const EmaColourArgs &a, int R, dim3 grid, size_t lds, hipStream_t s) {
   auto go = [&](auto kern) {
     if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    kern<<<grid, BLOCK, lds, s>>>(a);
+    kern<<<grid, NT, lds, s>>>(a);
   };
   switch (R) {
-    case 4: go(k_ema_colour<T, 4, SC>); return 0;
-    case 8: go(k_ema_colour<T, 8, SC>); return 0;
-    case 16: go(k_ema_colour<T, 16, SC>); return 0;
+    case 4: go(k_ema_colour<T, 4, SC, NT>); return 0;
+    case 8: go(k_ema_colour<T, 8, SC, NT>); return 0;
+    case 16: go(k_ema_colour<T, 16, SC, NT>); return 0;
     default: return -1;
   }
 }
 
-int launch_ema_colour(int dtype, const EmaColourArgs &a, int R, dim3 grid, size_t lds, hipStream_t s) {
-  if (dtype == DT_F32) return ema_colour_t<float, true>(a, R, grid, lds, s);
-  if (dtype == DT_F64) return ema_colour_t<double, false>(a, R, grid, lds, s);
-  return ema_colour_t<uint64_t, false>(a, R, grid, lds, s);
+template <typename T, bool SC>
+static int ema_colour_t(const EmaColourArgs &a, int R, int nt, dim3 grid, size_t lds, hipStream_t s) {
+  if (nt == 512) return ema_colour_nt<T, SC, 512>(a, R, grid, lds, s);
+  if (nt == 256) return ema_colour_nt<T, SC, 256>(a, R, grid, lds, s);
+  return -1;
+}
+
+int launch_ema_colour(int dtype, const EmaColourArgs &a, int R, int nt, dim3 grid, size_t lds, hipStream_t s) {
+  if (dtype == DT_F32) return ema_colour_t<float, true>(a, R, nt, grid, lds, s);
+  if (dtype == DT_F64) return ema_colour_t<double, false>(a, R, nt, grid, lds, s);
+  return ema_colour_t<uint64_t, false>(a, R, nt, grid, lds, s);
 }
 
 void launch_colmax(const float *X, int64_t n, int64_t ld, int64_t cols, unsigned *mx, hipStream_t s) {

@@ -1171,7 +1171,10 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g, bool *done) {
   ProfScope ps(SG2V_K_EMA_GENERAL,
                (double)x.g->n * x.b * (double)(nd.cols + nd.c_sa + nd.c_sb) * x.es,
                (double)x.g->n * x.b * (double)nd.c_u * nd.c_q, x.s);
-  if (launch_ema_colour(x.dt, a, R, dim3((unsigned)std::max<int64_t>(1, blocks), (unsigned)x.b), lds, x.s)) {
+  // wide outputs: 512 threads share each staged tile (each still has several
+  // output columns), narrow ones keep 256 so that few threads idle
+  const int nt = nd.cols >= 4 * 512 ? 512 : 256;
+  if (launch_ema_colour(x.dt, a, R, nt, dim3((unsigned)std::max<int64_t>(1, blocks), (unsigned)x.b), lds, x.s)) {
     set_error("sg2v_count: no colour-restricted eMA variant for R=%d", R);
     return SG2V_EINVAL;
   }
