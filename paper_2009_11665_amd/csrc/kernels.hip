@@ -1756,6 +1756,7 @@ template <typename T, bool SC>
 static int ema_colour_t(const EmaColourArgs &a, int R, int nt, dim3 grid, size_t lds, hipStream_t s) {
   if (nt == 512) return ema_colour_nt<T, SC, 512>(a, R, grid, lds, s);
   if (nt == 256) return ema_colour_nt<T, SC, 256>(a, R, grid, lds, s);
+  if (nt == 128) return ema_colour_nt<T, SC, 128>(a, R, grid, lds, s);
   return -1;
 }
 

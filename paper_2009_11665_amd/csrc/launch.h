@@ -157,7 +157,8 @@ void launch_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *color
 // rows grouped by colour: counts[j][c], then perm[j][.] (order within a colour is arbitrary)
 void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int32_t k, int32_t *counts,
                    int32_t *cursor, int32_t *perm, hipStream_t s);
-// nt: threads per block, 256 or 512 (the staged tile shared by more waves)
+// nt: threads per block, 128, 256 or 512 (about one output column per thread
+// or more; wide outputs share each staged tile among more waves)
 int launch_ema_colour(int dtype, const EmaColourArgs &a, int R, int nt, dim3 grid, size_t lds, hipStream_t s);
 
 // edge gradient: grad[e] += sum_c Bbar(i, c) * M_p(j, c) for e = (i -> j)

@@ -1165,15 +1165,17 @@ sg2v_status ema_colour(Ctx &x, int node, const EmaArgs &g, bool *done) {
   if (R < 4) R = 4;
   const size_t lds = lds_for(R);
   if (lds > x.lds_max) return SG2V_OK;  // staging does not fit: the general kernel runs
+  // wide outputs: 512 threads share each staged tile (each still has several
+  // output columns); narrow ones (256 columns or fewer) take 128 threads and
+  // twice the blocks per CU, so that few threads idle
+  const int nt = nd.cols >= 4 * 512 ? 512 : nd.cols <= 256 ? 128 : 256;
   const int64_t ntiles = x.g->n / R + k;
   const int64_t per_cu = std::max<int64_t>(1, (int64_t)(x.lds_max / lds));
-  const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8));
+  const int64_t blocks =
+      std::min<int64_t>(ntiles, (int64_t)x.cu_count * std::min<int64_t>(per_cu, 8 * 256 / nt));
   ProfScope ps(SG2V_K_EMA_GENERAL,
                (double)x.g->n * x.b * (double)(nd.cols + nd.c_sa + nd.c_sb) * x.es,
                (double)x.g->n * x.b * (double)nd.c_u * nd.c_q, x.s);
-  // wide outputs: 512 threads share each staged tile (each still has several
-  // output columns), narrow ones keep 256 so that few threads idle
-  const int nt = nd.cols >= 4 * 512 ? 512 : 256;
   if (launch_ema_colour(x.dt, a, R, nt, dim3((unsigned)std::max<int64_t>(1, blocks), (unsigned)x.b), lds, x.s)) {
     set_error("sg2v_count: no colour-restricted eMA variant for R=%d", R);
     return SG2V_EINVAL;
