@@ -835,6 +835,9 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
   const int r_first = threadIdx.x / W, cc_first = threadIdx.x - r_first * W;
   const int jj_first = cc_first / a.Cs, cl_first = cc_first - jj_first * a.Cs;
   const int dr = BLOCK / W, dcc = BLOCK - dr * W;
+  // offsets within a tile fit 32 bits: R * ld is about 4 * U * BLOCK * (ld / W),
+  // and ld / W (input or output columns over output columns) is at most 20
+  const int ldb32 = (int)a.ldb, lds32 = (int)a.lds;
   const int djj = dcc / a.Cs, dcl = dcc - djj * a.Cs;
   for (int64_t i0 = (int64_t)blockIdx.x * R; i0 < a.n; i0 += (int64_t)gridDim.x * R) {
     const int nrow = (int)min<int64_t>(R, a.n - i0);
@@ -846,14 +849,16 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
     }
     __syncthreads();
     int r = r_first, jc = jj_first, lc = cl_first;
+    const T *Btile = Bt + i0 * a.ldb;
+    T *Mtile = Ms + i0 * a.lds;
     for (int e0 = threadIdx.x; e0 < E; e0 += U * BLOCK) {
-      int64_t row[U];
+      int row[U];  // within the tile
       int jj[U], cl[U], cc[U], c[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         // entries past the tile load from its last row and store nothing
         const int rr = min(r, nrow - 1);
-        row[u] = i0 + rr;
+        row[u] = rr;
         jj[u] = jc;
         cl[u] = lc;
         cc[u] = jc * a.Cs + lc;
@@ -884,8 +889,8 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
       float f[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t src = (int64_t)jj[u] * a.Cb + max(idx[u], 0);
-        v[u] = Bt[row[u] * a.ldb + src];
+        const int src = jj[u] * a.Cb + max(idx[u], 0);
+        v[u] = Btile[row[u] * ldb32 + src];
         f[u] = SCALED ? a.fb[src] : 1.0f;
       }
 #pragma unroll
@@ -893,7 +898,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
         if (e0 + u * BLOCK < E) {
           T w = idx[u] >= 0 ? v[u] : T(0);
           if constexpr (SCALED) w *= f[u];
-          Ms[row[u] * a.lds + cc[u]] = w;
+          Mtile[row[u] * lds32 + cc[u]] = w;
           if (track && (float)w > 0.f) atomicMax(&lmx[cc[u]], __float_as_uint((float)w));
         }
       }
