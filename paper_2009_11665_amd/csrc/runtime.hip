@@ -55,6 +55,11 @@ sg2v_tuning_t tuning() {
 
 constexpr int64_t kSegment = 4096;  // neighbours per SpMM task (longer rows are split)
 constexpr int kPersistBlocks = 2048;
+// blocks of an SpMM launch with the neighbour-range split (512 per XCD): more
+// than one round of resident blocks, so that the blocks of a range that finish
+// early pick up the remaining units (2048: 284 ms, 4096: 278 ms, 8192: 283 ms
+// for the 15-vertex tree on RMAT scale 20)
+constexpr int kXsplitBlocks = 4096;
 constexpr int kRootBlocks = 2048;    // most root blocks (per-block partial sums)
 constexpr int kXsplit = 8;          // neighbour ranges (one per XCD)
 constexpr int64_t kXsplitMin = 512; // tasks at least this long are split by range
@@ -1019,7 +1024,8 @@ sg2v_status step_spmm(Ctx &x, int node) {
     a.tsplit = x.g->tsplit;
     a.n_tasks = U->x_tasks;
     a.partial8 = x.ws->xpart.p;
-    const int64_t gx = std::max<int64_t>(kXsplit, std::min<int64_t>(U->n_units * kXsplit, kPersistBlocks) / kXsplit * kXsplit);
+    const int64_t gx =
+        std::max<int64_t>(kXsplit, std::min<int64_t>(U->n_units * kXsplit, kXsplitBlocks) / kXsplit * kXsplit);
     for (int64_t c0 = 0; c0 < chunks; c0 += gch) {
       const int64_t gc = std::min(gch, chunks - c0);
       const double frac = (double)gc / (double)chunks;
