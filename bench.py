@@ -180,7 +180,7 @@ def batch_workload(sg, gg, torch, reps=3):
         torch.cuda.synchronize()
         t_seq = (time.perf_counter() - t0) / reps
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
     return {
         "workload": "chung-lu n=500000 d=20 gamma=2.1; bintree7, path8, caterpillar10 (k=t, re-rooted) x 16 colourings, fp32s",
         "template_colorings_per_s": 3 * ncol / t_graph,
@@ -362,7 +362,7 @@ def main():
             torch.cuda.synchronize()
             t3 = time.perf_counter()
         finally:
-            sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+            sg.restore_tuning(old)
         fp64 = {"value": ncol * args.fp64_steps / (t3 - t2), "unit": "colorings/s",
                 "ms_per_step": (t3 - t2) / args.fp64_steps * 1e3}
         err = max(abs(a - b) / abs(b) for a, b in zip(res32["colorful"], r64["colorful"]) if b)

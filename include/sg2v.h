@@ -4,9 +4,9 @@
  * C ABI of the library libsg2v.so.  It implements the decoupled dynamic
  * programme of SubGraph2Vec (Zhang et al., arXiv 2009.11665): for every
  * colouring of the graph and every split of the template into an active and
- * a passive sub-template, a neighbour aggregation B = A_G M_p (Sec. 4.1,
+ * a passive sub-template, a neighbour aggregation B = A_G M_p (Sec. 5.1,
  * Alg. 4, Eq. 1) followed by an element-wise multiply-add of B with the
- * active table through colour-set split tables (Sec. 4.3, Alg. 5).  The
+ * active table through colour-set split tables (Sec. 5.3, Alg. 5).  The
  * colourful count of each colouring is scaled by 1/(P alpha) (Alg. 1).
  *
  * Conventions
@@ -262,7 +262,10 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
  * ema_rows: rows per eMA tile; batch: colourings per pass; flags:
  * SG2V_TUNE_NO_COLOR_SKIP disables the colour-based skipping of SpMM row
  * segments, SG2V_TUNE_NO_COLOR_EMA the colour-restricted multiply-add
- * (vertices grouped by colour); budget_bytes: device memory the count may use. */
+ * (vertices grouped by colour); budget_bytes: device memory the count may use;
+ * xsplit_group and launch_chunks bound the column chunks one SpMM launch
+ * covers (a table wider than that takes several launches, each starting at a
+ * later chunk). */
 #define SG2V_TUNE_NO_COLOR_SKIP 1
 #define SG2V_TUNE_NO_COLOR_EMA 2
 #define SG2V_TUNE_SPMM_UNROLL4 4 /* 4 row gathers in flight per SpMM stream (default below a mean
@@ -290,6 +293,10 @@ typedef struct {
   int32_t batch;
   int32_t flags;
   int64_t budget_bytes;
+  int32_t xsplit_group;  /* column chunks per launch of the neighbour-range split
+                            (0: as many as 8 GB of range-partial rows hold) */
+  int32_t launch_chunks; /* column chunks per SpMM launch without the split
+                            (0: 65,535, the grid limit) */
 } sg2v_tuning_t;
 
 sg2v_status sg2v_set_tuning(const sg2v_tuning_t *t);
@@ -297,7 +304,10 @@ sg2v_status sg2v_get_tuning(sg2v_tuning_t *t);
 
 /* Autotuner: time sg2v_count of `plan` on `g` (n_colorings probe colourings,
  * `mode`) over a small set of candidate settings -- SpMM chunk width, colour
- * skipping, eMA rows per tile, colourings per pass -- and install the fastest
+ * skipping, gathers in flight, neighbour-range split, eMA rows per tile,
+ * colourings per pass; widths that give the same row segments are tried once;
+ * each candidate runs once untimed, then the median of three timed runs
+ * counts -- and install the fastest
  * with sg2v_set_tuning.  Results are cached per (template, n, nnz, mode,
  * n_colorings) in the process and, if the environment variable
  * SG2V_TUNE_CACHE names a file, in that file (one line per key).

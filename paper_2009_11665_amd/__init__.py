@@ -58,7 +58,8 @@ class NodeInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("spmm_width", ctypes.c_int32), ("ema_rows", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("budget_bytes", ctypes.c_int64)]
+                ("budget_bytes", ctypes.c_int64), ("xsplit_group", ctypes.c_int32),
+                ("launch_chunks", ctypes.c_int32)]
 
 
 EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_destroy",
@@ -342,9 +343,31 @@ TUNE_BATCH_SERIAL = 512
 
 
 def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,
-               flags: int = 0):
-    t = Tuning(spmm_width, ema_rows, batch, flags, budget_bytes)
+               flags: int = 0, xsplit_group: int = 0, launch_chunks: int = 0):
+    t = Tuning(spmm_width, ema_rows, batch, flags, budget_bytes, xsplit_group, launch_chunks)
     _check(lib().sg2v_set_tuning(ctypes.byref(t)), "sg2v_set_tuning")
+
+
+def restore_tuning(t: Tuning):
+    """Install a Tuning returned by get_tuning() (or autotune())."""
+    _check(lib().sg2v_set_tuning(ctypes.byref(t)), "sg2v_set_tuning")
+
+
+class tuned:
+    """Context manager: ``with tuned(flags=..., spmm_width=...):`` installs
+    the settings and restores the previous ones on exit."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+
+    def __enter__(self):
+        self.old = get_tuning()
+        set_tuning(**self.kw)
+        return self
+
+    def __exit__(self, *exc):
+        restore_tuning(self.old)
+        return False
 
 
 def get_tuning() -> Tuning:

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
 
 // ===========================================================================
 // BEGIN k_spmm
-// Neighbour aggregation B = A_G M_p (Sec. 4.1, Alg. 4; the SpMV step of Alg. 5) as a
+// Neighbour aggregation B = A_G M_p (Sec. 5.1, Alg. 4; the SpMV step of Alg. 5) as a
 // CSR SpMM over one column chunk of W = G * N columns per blockIdx.y.
 //
 // Rows are cut into tasks of at most a fixed number of neighbours (long rows

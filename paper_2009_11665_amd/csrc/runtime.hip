@@ -45,7 +45,7 @@ namespace {
 // ---------------------------------------------------------------------------
 // tuning
 
-sg2v_tuning_t g_tune = {0, 0, 0, 0, 0};
+sg2v_tuning_t g_tune = {0, 0, 0, 0, 0, 0, 0};
 std::mutex g_tune_mu;
 
 sg2v_tuning_t tuning() {
@@ -67,6 +67,12 @@ constexpr double kXpartBytes = 8.0 * (1 << 30);  // range-partial rows of one ch
 // graphs whose 128-byte column chunk (n rows) reaches 32 MB: wider chunks and
 // the neighbour-range split by default
 bool large_graph(int64_t n) { return (double)n * 128.0 >= 32.0 * (1 << 20); }
+
+// column chunks per SpMM launch without the neighbour-range split
+int64_t fl_launch_chunks() {
+  const sg2v_tuning_t tu = tuning();
+  return tu.launch_chunks > 0 ? std::min<int64_t>(tu.launch_chunks, 65535) : 65535;
+}
 
 int dtype_of(sg2v_mode m) { return m == SG2V_FP32S ? DT_F32 : (m == SG2V_FP64 ? DT_F64 : DT_U64); }
 int esize_of(int dt) { return dt == DT_F32 ? 4 : 8; }
@@ -929,8 +935,10 @@ sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t 
   }
   const int64_t chunks = (nc + W - 1) / W;
   const double per_chunk = (double)kXsplit * U->x_tasks * W * x.es;
+  int64_t cap = (int64_t)65535;
+  if (tu.xsplit_group > 0) cap = std::min<int64_t>(cap, tu.xsplit_group);
   const int64_t gch = std::max<int64_t>(
-      1, std::min<int64_t>({chunks, (int64_t)65535, (int64_t)(kXpartBytes / per_chunk)}));
+      1, std::min<int64_t>({chunks, cap, (int64_t)(kXpartBytes / per_chunk)}));
   ST_TRY(x.ws->xpart.ensure((size_t)(per_chunk * gch) + 256));
   *group = gch;
   return SG2V_OK;
@@ -1003,8 +1011,9 @@ sg2v_status step_spmm(Ctx &x, int node) {
                        (double)chunks * (nnz * (4.0 + (x.g->w ? 4.0 : 0.0)) + 20.0 * x.g->n_tasks);
   if (gch == 0) {
     // all chunks in one launch (grid.y is at most 65535: groups beyond that)
-    for (int64_t c0 = 0; c0 < chunks; c0 += 65535) {
-      const int64_t gc = std::min<int64_t>(65535, chunks - c0);
+    const int64_t per_launch = fl_launch_chunks();
+    for (int64_t c0 = 0; c0 < chunks; c0 += per_launch) {
+      const int64_t gc = std::min<int64_t>(per_launch, chunks - c0);
       const double frac = (double)gc / (double)chunks;
       a.chunk0 = c0;
       dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)), (unsigned)gc);
@@ -1680,7 +1689,8 @@ std::vector<std::unique_ptr<BatchGraph>> g_batch_cache;
 
 bool same_tuning(const sg2v_tuning_t &a, const sg2v_tuning_t &b) {
   return a.spmm_width == b.spmm_width && a.ema_rows == b.ema_rows && a.batch == b.batch &&
-         a.flags == b.flags && a.budget_bytes == b.budget_bytes;
+         a.flags == b.flags && a.budget_bytes == b.budget_bytes &&
+         a.xsplit_group == b.xsplit_group && a.launch_chunks == b.launch_chunks;
 }
 
 void ws_gens(Workspace &ws, uint64_t *out) {
@@ -2496,7 +2506,8 @@ void tune_file_load() {
   std::ifstream in(f);
   std::string key;
   sg2v_tuning_t t{};
-  while (in >> key >> t.spmm_width >> t.ema_rows >> t.batch >> t.flags >> t.budget_bytes)
+  while (in >> key >> t.spmm_width >> t.ema_rows >> t.batch >> t.flags >> t.budget_bytes >>
+         t.xsplit_group >> t.launch_chunks)
     g_autotune[key] = t;
 }
 
@@ -2505,7 +2516,7 @@ void tune_file_store(const std::string &key, const sg2v_tuning_t &t) {
   if (!f) return;
   std::ofstream out(f, std::ios::app);
   out << key << " " << t.spmm_width << " " << t.ema_rows << " " << t.batch << " " << t.flags
-      << " " << t.budget_bytes << "\n";
+      << " " << t.budget_bytes << " " << t.xsplit_group << " " << t.launch_chunks << "\n";
 }
 
 }  // namespace
@@ -2547,15 +2558,40 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
       t.flags = (base.flags & ~skipfl) | fl;
       cand.push_back(t);
     }
+  // candidates whose chunk width maps to the same row-segment lanes run the
+  // same kernels: keep the first of each
+  {
+    int64_t widest = 1;
+    for (auto &nd : plan->p.nodes)
+      if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? (int64_t)plan->p.k : nd.cols);
+    const int dt = dtype_of(mode);
+    std::vector<std::pair<int, int>> seen;
+    std::vector<sg2v_tuning_t> uniq;
+    for (auto &t : cand) {
+      ST_TRY(sg2v_set_tuning(&t));
+      const std::pair<int, int> key(pick_G(dt, widest, g->n), t.flags);
+      if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+      seen.push_back(key);
+      uniq.push_back(t);
+    }
+    ST_TRY(sg2v_set_tuning(&base));
+    cand.swap(uniq);
+  }
   sg2v_tuning_t best = base;
   double best_ms = 1e300;
+  // one untimed count, then the median of three timed ones
   auto time_one = [&](const sg2v_tuning_t &t, double *ms) -> sg2v_status {
     ST_TRY(sg2v_set_tuning(&t));
     double cf;
     ST_TRY(sg2v_count(plan, g, c, mode, stream, nullptr, nullptr, nullptr, &cf, nullptr));
-    auto t0 = std::chrono::steady_clock::now();
-    ST_TRY(sg2v_count(plan, g, c, mode, stream, nullptr, nullptr, nullptr, &cf, nullptr));
-    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    double v[3];
+    for (double &x : v) {
+      auto t0 = std::chrono::steady_clock::now();
+      ST_TRY(sg2v_count(plan, g, c, mode, stream, nullptr, nullptr, nullptr, &cf, nullptr));
+      x = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    std::sort(v, v + 3);
+    *ms = v[1];
     return SG2V_OK;
   };
   sg2v_status st = SG2V_OK;

@@ -142,7 +142,7 @@ def test_tuning_roundtrip():
         t = sg.get_tuning()
         assert (t.spmm_width, t.ema_rows, t.batch, t.budget_bytes) == (64, 8, 3, 123456)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
 
 
 def _edges(par):

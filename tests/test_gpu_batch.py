@@ -33,7 +33,7 @@ def test_batch_equals_single_and_oracle(flags):
     try:
         _batch_vs_single(G, g, plans, seed, ncol)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
 
 
 def _batch_vs_single(G, g, plans, seed, ncol):
@@ -92,7 +92,7 @@ def test_batch_config_chung_lu_500k():
     """The batching workload: Chung-Lu n=500,000, mean degree 20, gamma 2.1;
     bintree7, path8, caterpillar10 x 16 colourings in one graph launch, FP32
     with per-column scaling, against the FP64 path (all colourings) and the
-    oracle (first colouring of bintree7 and path8)."""
+    oracle (first colouring of every template)."""
     G = gg.chung_lu_500k()
     g = sg.Graph.from_csr(G)
     plans = [sg.Plan(p) for p in TEMPLATES]
@@ -100,7 +100,7 @@ def test_batch_config_chung_lu_500k():
     cf32, est32 = sg.count_batch(plans, g, seed, ncol, "fp32s")
     cf64, _ = sg.count_batch(plans, g, seed, ncol, "fp64")
     np.testing.assert_allclose(cf32, cf64, rtol=1e-5)
-    for p, par in enumerate(TEMPLATES[:2]):
+    for p, par in enumerate(TEMPLATES):
         k = len(par)
         f = O.count(G, par, k, O.colors(G.n, k, seed, 0))[0]
         say("oracle", par, f, cf64[p][0])
@@ -120,7 +120,7 @@ def test_autotune_installs_a_candidate_and_keeps_results():
         cur = sg.get_tuning()
         assert (cur.spmm_width, cur.ema_rows, cur.batch, cur.flags) == (
             t.spmm_width, t.ema_rows, t.batch, t.flags)
-        assert t.spmm_width in (16, 32, 64)
+        assert t.spmm_width in (16, 32, 64, 128)  # the autotuner's candidate widths
         np.testing.assert_array_equal(sg.count(p, g, c, "u64")["colorful_u64"], ref)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)

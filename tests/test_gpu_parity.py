@@ -117,7 +117,7 @@ def test_rerooted_template_same_counts(small_rmat, par, flags):
             for j in range(2):
                 assert rf["colorful"][j] == pytest.approx(float(ref[j][1]), rel=tol)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
 
 
 def test_staged_root_several_tiles_per_block():
@@ -190,7 +190,7 @@ def test_intermediate_tables(small_rmat, mode, skip):
                         got = np.where(holds, got.dtype.type(0), got)
                     _cmp(got, ref_B, mode)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
 
 
 def _cmp(got, ref, mode):
@@ -233,7 +233,7 @@ def test_batching_invariance(small_rmat):
         np.testing.assert_array_equal(res[1], res[5])
         np.testing.assert_allclose(res[("f", 1)], res[("f", 5)], rtol=1e-6)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
 
 
 def test_spmm_widths_agree(small_rmat):
@@ -256,7 +256,7 @@ def test_spmm_widths_agree(small_rmat):
                 got = sg.count(p, g, c, "u64")["colorful_u64"]
                 assert [int(x) for x in got] == ref
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
 
 
 def test_edge_cases():
@@ -294,7 +294,7 @@ def test_budget_too_small_is_enomem():
             sg.count(p, g, c, "fp32s")
         assert e.value.status == -4
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
     r = sg.count(p, g, c, "u64")
     assert int(r["colorful_u64"][0]) == O.count(G, gg.CATERPILLAR10, 10, O.colors(G.n, 10, 1, 0), mode=O.U64)[1]
 
@@ -325,7 +325,7 @@ def test_long_rows_split_across_tasks(flags):
                 assert int(r["colorful_u64"][j]) == ref[j][1]
                 assert r32["colorful"][j] == pytest.approx(ref64[j][0], rel=FP32_TOL)
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
 
 
 def test_u64_overflow_flag():
@@ -359,7 +359,7 @@ def test_mid_config_rmat16_bintree7():
     assert ru["overflow"] == any(x[2] for x in refu)
 
 
-def test_bintree15_on_rmat14_against_oracle():
+def test_bintree15_on_rmat12_against_oracle():
     """The large configuration's template (15-vertex binary tree, k = 15) on a
     smaller RMAT graph that the oracle finishes: FP32S and FP64 vs oracle."""
     G = gg.rmat(12, 60_000, seed=5)
@@ -388,7 +388,7 @@ def test_bintree15_u64_exact_both_root_paths(flags):
         r = gpu_counts(G, par, k, 9, 2, "u64")
         r32 = gpu_counts(G, par, k, 9, 2, "fp32s")
     finally:
-        sg.set_tuning(old.spmm_width, old.ema_rows, old.batch, old.budget_bytes, old.flags)
+        sg.restore_tuning(old)
     say("bt15 u64", flags, ref, list(r["colorful_u64"]))
     assert [int(x) for x in r["colorful_u64"]] == ref
     np.testing.assert_allclose(r32["colorful"], ref64, rtol=FP32_TOL)
@@ -483,3 +483,39 @@ def test_many_colourings_per_pass(mode):
             assert int(r["colorful_u64"][j]) == u, j
         else:
             assert r["colorful"][j] == pytest.approx(float(u), rel=FP64_TOL if mode == "fp64" else FP32_TOL), j
+
+
+@pytest.mark.parametrize("split", [True, False])
+def test_spmm_chunk_groups_against_oracle(split):
+    """A wide table aggregated in several SpMM launches, each starting at a
+    later column chunk, as on the large workload: with the neighbour-range
+    split over 256-byte row segments in chunk groups of 3 chunks (the
+    6435-column table of the 15-vertex tree takes 34 launches plus their
+    range combines, every launch after the first with a column offset), and
+    without the split in launches of 2 chunks.  U64 exact (mod 2^64) and FP32S
+    within 1e-5 of the FP64 oracle."""
+    G = gg.rmat(12, 60_000, seed=5)
+    assert (G.degrees() >= 512).sum() > 0  # tasks the range split applies to
+    par, k, seed = gg.BINTREE15, 15, 3
+    col = O.colors(G.n, k, seed, 0)
+    _, ref_u, _ = O.count(G, par, k, col, mode=O.U64)
+    ref_f, _, _ = O.count(G, par, k, col, mode=O.FP64)
+    kw = (dict(spmm_width=64, flags=sg.TUNE_XSPLIT | sg.TUNE_FORCE_XSPLIT, xsplit_group=3) if split
+          else dict(spmm_width=64, flags=sg.TUNE_NO_XSPLIT, launch_chunks=2))
+    g = sg.Graph.from_csr(G)
+    c = sg.Colorings(g, k, seed, 1)
+    p = sg.Plan(par, k)
+    with sg.tuned(**kw):
+        for mode in ("u64", "fp32s"):
+            say("chunk groups", "split" if split else "plain", mode)
+            sg.profile_start()
+            r = sg.count(p, g, c, mode)
+            prof = sg.profile_stop()
+            # 101 chunks of the 6435-column table + 8 of the 455-column one
+            assert prof["spmm"]["launches"] >= (34 + 3 if split else 51 + 4), prof["spmm"]
+            if split:
+                assert prof["spmm_combine"]["launches"] >= 34 + 3
+            if mode == "u64":
+                assert int(r["colorful_u64"][0]) == ref_u
+            else:
+                assert r["colorful"][0] == pytest.approx(ref_f, rel=FP32_TOL)
