@@ -193,6 +193,28 @@ sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_co
                        sg2v_mode mode, void *stream, double *colorful, uint64_t *colorful_u64,
                        double *estimate, double *mean_estimate, int32_t *overflow);
 
+/* sg2v_count for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as sg2v_count, with the same kernels; it
+ * calls no hipMalloc, hipFree or other allocating routine.  Every buffer of
+ * the count (tables, partial sums, colour-skip masks, results) is taken from
+ * one scratch area of SG2V_NOALLOC_SCRATCH_BYTES in the library's device
+ * memory, one area per device, held from the first call on that device until
+ * the process ends.  Colourings per pass are halved until a pass fits; a
+ * count whose single-colouring pass does not fit returns SG2V_ENOMEM with the
+ * size it needed.
+ * Set-up: the plan's split tables must already be on the device (one
+ * sg2v_count call with the plan on that device uploads them; SG2V_ENOMEM
+ * otherwise).  The graph's task tables are made by sg2v_graph_create.
+ * Every call on one device shares its area, which keeps the last call's
+ * contents: calls that overlap on one device (other threads, other streams)
+ * race.  The call synchronises `stream` before it returns. */
+#define SG2V_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sg2v_status sg2v_count_noalloc(const sg2v_plan *plan, const sg2v_graph *g,
+                               const sg2v_colorings *c, sg2v_mode mode, void *stream,
+                               double *colorful, uint64_t *colorful_u64, double *estimate,
+                               double *mean_estimate, int32_t *overflow);
+
 /* Several templates over n_colorings colourings each (colourings
  * seed-derived per plan: sg2v_color(g, k_p, seed, 0, n_colorings)), run as
  * one captured device graph.  colorful/estimate: n_plans x n_colorings,

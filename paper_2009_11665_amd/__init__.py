@@ -67,7 +67,8 @@ EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_des
            "sg2v_plan_info", "sg2v_plan_node", "sg2v_plan_pairs", "sg2v_graph_create", "sg2v_graph_destroy",
            "sg2v_color", "sg2v_colorings_destroy", "sg2v_colorings_download", "sg2v_count",
            "sg2v_count_batch", "sg2v_count_grad", "sg2v_debug_table", "sg2v_set_tuning",
-           "sg2v_get_tuning", "sg2v_profile_start", "sg2v_profile_stop", "sg2v_autotune"]
+           "sg2v_get_tuning", "sg2v_profile_start", "sg2v_profile_stop", "sg2v_autotune",
+           "sg2v_count_noalloc"]
 
 KERNEL_KINDS = ["color", "hist", "spmm", "spmm_combine", "ema_general", "ema_single", "root"]
 
@@ -111,6 +112,7 @@ def lib():
         L.sg2v_colorings_destroy.restype = None
         L.sg2v_colorings_download.argtypes = [P, P, P]
         L.sg2v_count.argtypes = [P, P, P, i32, P, P, P, P, P, P]
+        L.sg2v_count_noalloc.argtypes = [P, P, P, i32, P, P, P, P, P, P]
         L.sg2v_count_batch.argtypes = [P, i32, P, u64, i32, i32, P, P, P]
         L.sg2v_count_grad.argtypes = [P, P, P, i32, P, P, P]
         L.sg2v_debug_table.argtypes = [P, P, P, i32, i32, i32, i32, P, P]
@@ -289,6 +291,28 @@ def count(plan: Plan, graph: Graph, col: Colorings, mode="fp32s", stream=None):
                             _ptr(est), ctypes.byref(mean), ctypes.byref(ovf)), "sg2v_count")
     return dict(colorful=cf, colorful_u64=cu, estimate=est, mean_estimate=mean.value,
                 overflow=bool(ovf.value))
+
+
+def count_noalloc(plan: Plan, graph: Graph, col: Colorings, mode="fp32s", stream=None):
+    """As count(), through sg2v_count_noalloc: no device allocation; every
+    buffer comes from the library's fixed scratch area
+    (NOALLOC_SCRATCH_BYTES per device).  The plan must have been counted once
+    with count() on this device."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    n = col.count
+    cf = np.zeros(n, np.float64)
+    cu = np.zeros(n, np.uint64)
+    est = np.zeros(n, np.float64)
+    mean = ctypes.c_double(0)
+    ovf = ctypes.c_int32(0)
+    _check(lib().sg2v_count_noalloc(plan.h, graph.h, col.h, m, _stream(stream), _ptr(cf), _ptr(cu),
+                                    _ptr(est), ctypes.byref(mean), ctypes.byref(ovf)),
+           "sg2v_count_noalloc")
+    return dict(colorful=cf, colorful_u64=cu, estimate=est, mean_estimate=mean.value,
+                overflow=bool(ovf.value))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def count_batch(plans: Sequence[Plan], graph: Graph, seed: int, n_colorings: int, mode="fp32s",

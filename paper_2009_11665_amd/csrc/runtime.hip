@@ -79,15 +79,50 @@ int esize_of(int dt) { return dt == DT_F32 ? 4 : 8; }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// A fixed device area handed out front to back (sg2v_count_noalloc): buffers
+// taken from it are never allocated or freed.
+struct Carver {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t top = 0;
+  bool exhausted = false;  // a request did not fit
+};
+
+// Set while sg2v_count_noalloc runs on this thread: device allocations fail
+// with a message instead of calling hipMalloc.
+thread_local bool t_noalloc = false;
+
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
   uint64_t gen = 0;  // bumped on every reallocation (captured graphs hold raw pointers)
+  Carver *cv = nullptr;  // set: carved from a fixed area instead of hipMalloc
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p && !cv) (void)hipFree(p);
   }
   sg2v_status ensure(size_t want) {
     if (want <= bytes) return SG2V_OK;
+    if (cv) {
+      want = (want + 255) / 256 * 256;
+      // the most recent buffer of the area grows in place, any other moves to the top
+      size_t off = (p && (char *)p + bytes == cv->base + cv->top) ? (size_t)((char *)p - cv->base)
+                                                                  : cv->top;
+      if (off + want > cv->cap) {
+        cv->exhausted = true;
+        set_error("sg2v_count_noalloc: the count needs more than the %zu-byte scratch area "
+                  "(%zu bytes requested at offset %zu)", cv->cap, want, off);
+        return SG2V_ENOMEM;
+      }
+      p = cv->base + off;
+      bytes = want;
+      cv->top = off + want;
+      ++gen;
+      return SG2V_OK;
+    }
+    if (t_noalloc) {
+      set_error("sg2v_count_noalloc: a device allocation of %zu bytes was requested", want);
+      return SG2V_ENOMEM;
+    }
     if (p) {
       (void)hipFree(p);
       p = nullptr;
@@ -110,6 +145,11 @@ template <typename T>
 sg2v_status upload(const std::vector<T> &h, void **d, hipStream_t s) {
   *d = nullptr;
   if (h.empty()) return SG2V_OK;
+  if (t_noalloc) {
+    set_error("sg2v_count_noalloc: device tables of the plan or graph are not set up on this "
+              "device; one sg2v_count call with the same plan and graph sets them up");
+    return SG2V_ENOMEM;
+  }
   HIP_TRY(hipMalloc(d, h.size() * sizeof(T)));
   HIP_TRY(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return SG2V_OK;
@@ -154,7 +194,7 @@ struct ProfScope {
   ProfRec r;
   hipStream_t s;
   ProfScope(int kind, double bytes, double work, hipStream_t st)
-      : on(profiler().on && !t_capturing), s(st) {
+      : on(profiler().on && !t_capturing && !t_noalloc), s(st) {
     if (!on) return;
     r.kind = kind;
     r.bytes = bytes;
@@ -438,6 +478,11 @@ extern "C" sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *
     }
   }
   ST_TRY(graph_tasks(g.get(), rp, s));
+  // task units for every row-segment width, so that counts never upload them
+  for (int G = 2; G <= 32; G *= 2) {
+    UnitTable *U = nullptr;
+    ST_TRY(build_units(g.get(), G, s, &U));
+  }
   *out = g.release();
   return SG2V_OK;
 }
@@ -779,6 +824,9 @@ struct Ctx {
   int bucket_b = 0;
   int nbr_j0 = -1;     // pass whose neighbour colours are in ws->nbrcol
   int nbr_b = 0;
+  // sg2v_count_noalloc: colour-skip masks copied into the scratch area
+  std::map<std::tuple<int, int, int>, void *> tmp_masks;
+  std::vector<std::vector<uint32_t>> tmp_host;
 };
 
 sg2v_status bind_tables(Ctx &x) {
@@ -885,7 +933,12 @@ sg2v_status chunk_masks(Ctx &x, int node, int W, const int32_t **jb, const uint3
   const int64_t C = nd.cols, nc = C * x.b, nch = (nc + W - 1) / W;
   auto key = std::make_tuple(node, x.b, W);
   auto it = D->chunks.find(key);
-  if (it == D->chunks.end()) {
+  const void *found = it != D->chunks.end() ? it->second : nullptr;
+  if (!found) {
+    auto tk = x.tmp_masks.find(key);
+    if (tk != x.tmp_masks.end()) found = tk->second;
+  }
+  if (!found) {
     std::vector<uint32_t> h((size_t)nch * 3);
     for (int64_t ch = 0; ch < nch; ++ch) {
       const int64_t c0 = ch * W, c1 = std::min<int64_t>(c0 + W, nc);
@@ -902,11 +955,28 @@ sg2v_status chunk_masks(Ctx &x, int node, int W, const int32_t **jb, const uint3
       h[2 * nch + ch] = i;
     }
     void *d = nullptr;
-    ST_TRY(upload(h, &d, x.s));
-    HIP_TRY(hipStreamSynchronize(x.s));
-    it = D->chunks.emplace(key, d).first;
+    if (t_noalloc && x.ws->arena.cv) {
+      // into the scratch area for this call; the host copy lives until the call ends
+      Carver *cv = x.ws->arena.cv;
+      const size_t bytes = (h.size() * 4 + 255) / 256 * 256;
+      if (cv->top + bytes > cv->cap) {
+        cv->exhausted = true;
+        set_error("sg2v_count_noalloc: the count needs more than the %zu-byte scratch area", cv->cap);
+        return SG2V_ENOMEM;
+      }
+      d = cv->base + cv->top;
+      cv->top += bytes;
+      HIP_TRY(hipMemcpyAsync(d, h.data(), h.size() * 4, hipMemcpyHostToDevice, x.s));
+      x.tmp_host.push_back(std::move(h));
+      x.tmp_masks[key] = d;
+    } else {
+      ST_TRY(upload(h, &d, x.s));
+      HIP_TRY(hipStreamSynchronize(x.s));
+      D->chunks.emplace(key, d);
+    }
+    found = d;
   }
-  const uint32_t *base = (const uint32_t *)it->second;
+  const uint32_t *base = (const uint32_t *)found;
   *jb = (const int32_t *)base;
   *un = base + nch;
   *in = base + 2 * nch;
@@ -928,6 +998,7 @@ sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t 
   if (!(fl & SG2V_TUNE_FORCE_XSPLIT) && (!wanted || (double)x.g->n * W * x.es < 32.0 * (1 << 20)))
     return SG2V_OK;
   sg2v_graph *g = x.g;
+  if (!g->tsplit && t_noalloc) return SG2V_OK;  // offsets never built: no split (same counts)
   if (!g->tsplit) {
     HIP_TRY(hipMalloc((void **)&g->tsplit, (size_t)g->n_tasks * (kXsplit + 1) * sizeof(uint16_t)));
     launch_task_split(g->col_idx, g->task_beg, g->task_len, g->n_tasks, g->n, kXsplit, g->tsplit, x.s);
@@ -1617,6 +1688,130 @@ extern "C" sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g,
                            ncol * 8, hipMemcpyDeviceToHost, s));
     if (dt == DT_F32) HIP_TRY(hipMemcpyAsync(Eh.data(), Ed, ncol * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&ovf_h, x.ovf, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  finish_counts(P, ncol, P.root_kind == ROOT_VERTEX ? DT_F64 : dt, raw_f.data(), raw_u.data(),
+                Eh.data(), colorful, colorful_u64, estimate, mean_estimate);
+  if (colorful_u64 && P.root_kind == ROOT_VERTEX)
+    for (int j = 0; j < ncol; ++j) colorful_u64[j] = raw_u[j];
+  if (overflow) *overflow = ovf_h;
+  return SG2V_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sg2v_count without device allocations: every per-call buffer is carved
+// from a fixed area in the library's own device memory.
+
+namespace {
+
+// The area itself.  In host code its name is only a handle for
+// hipGetSymbolAddress; kernels receive the device address from scratch_area().
+static __device__ __align__(256) unsigned char scratch[SG2V_NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on device `dev` (which must be current), looked
+// up once per device and kept.
+sg2v_status scratch_area(int dev, char **out) {
+  static std::mutex mu;
+  static std::map<int, char *> ptrs;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptrs.find(dev);
+  if (it == ptrs.end()) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      set_error("sg2v_count_noalloc: hipGetSymbolAddress of the scratch area failed on device %d: %s",
+                dev, hipGetErrorString(e));
+      return SG2V_EDEVICE;
+    }
+    it = ptrs.emplace(dev, (char *)p).first;
+  }
+  *out = it->second;
+  return SG2V_OK;
+}
+
+struct NoallocGuard {
+  NoallocGuard() { t_noalloc = true; }
+  ~NoallocGuard() { t_noalloc = false; }
+};
+
+}  // namespace
+
+extern "C" sg2v_status sg2v_count_noalloc(const sg2v_plan *plan, const sg2v_graph *g,
+                                          const sg2v_colorings *c, sg2v_mode mode, void *stream,
+                                          double *colorful, uint64_t *colorful_u64,
+                                          double *estimate, double *mean_estimate,
+                                          int32_t *overflow) {
+  ST_TRY(check_inputs(plan, g, c, mode));
+  const Plan &P = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  const int ncol = c->count;
+  const int dt = dtype_of(mode);
+  std::vector<double> raw_f(ncol, 0.0);
+  std::vector<uint64_t> raw_u(ncol, 0);
+  std::vector<int> Eh(ncol, 0);
+  int ovf_h = 0;
+  if (P.root_kind == ROOT_VERTEX) {
+    for (int j = 0; j < ncol; ++j) {
+      raw_f[j] = (double)g->n;
+      raw_u[j] = (uint64_t)g->n;
+    }
+  } else {
+    {
+      std::lock_guard<std::mutex> lk(P.mu);
+      bool have = false;
+      for (auto &d : P.dev) have |= d.device == g->device;
+      if (!have) {
+        set_error("sg2v_count_noalloc: the plan's split tables are not on device %d yet; one "
+                  "sg2v_count call with this plan on this device uploads them", g->device);
+        return SG2V_ENOMEM;
+      }
+    }
+    char *area = nullptr;
+    ST_TRY(scratch_area(g->device, &area));
+    NoallocGuard guard;
+    Carver cv;
+    cv.base = area;
+    cv.cap = SG2V_NOALLOC_SCRATCH_BYTES;
+    Workspace ws;
+    DevBuf *bufs[] = {&ws.arena, &ws.small, &ws.partial, &ws.result, &ws.ovf,
+                      &ws.grad,  &ws.bucket, &ws.nbrcol, &ws.xpart};
+    // colourings per pass: as sg2v_count would take them, halved until the pass fits
+    int b = choose_batch(P, ncol, dt, g->n, g->n_slots);
+    std::unique_ptr<Ctx> x;
+    for (;;) {
+      cv.top = 0;
+      cv.exhausted = false;
+      for (DevBuf *d : bufs) {
+        d->p = nullptr;
+        d->bytes = 0;
+        d->cv = &cv;
+      }
+      x.reset(new Ctx());
+      sg2v_status st = prepare(*x, plan, (sg2v_graph *)g, c, mode, b, s, PassOpts(), &ws);
+      if (st == SG2V_OK) st = prewarm(*x, b);
+      if (st == SG2V_OK) st = prewarm(*x, ncol % b);
+      if (st == SG2V_OK) st = ws.result.ensure((size_t)ncol * 12 + 64);
+      if (st == SG2V_OK) break;
+      if (!cv.exhausted || b == 1) {
+        HIP_TRY(hipStreamSynchronize(s));  // mask copies read host memory of this call
+        return st;
+      }
+      HIP_TRY(hipStreamSynchronize(s));
+      b = (b + 1) / 2;
+    }
+    void *res = ws.result.p;
+    int *Ed = (int *)((char *)res + (size_t)ncol * 8);
+    launch_fill_u32((unsigned *)x->ovf, 1, 0u, s);
+    sg2v_status st = enqueue_count(*x, ncol, b, res, Ed);
+    if (st != SG2V_OK) {
+      (void)hipStreamSynchronize(s);
+      return st;
+    }
+    HIP_TRY(hipMemcpyAsync(dt == DT_U64 ? (void *)raw_u.data() : (void *)raw_f.data(), res,
+                           ncol * 8, hipMemcpyDeviceToHost, s));
+    if (dt == DT_F32) HIP_TRY(hipMemcpyAsync(Eh.data(), Ed, ncol * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ovf_h, x->ovf, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   finish_counts(P, ncol, P.root_kind == ROOT_VERTEX ? DT_F64 : dt, raw_f.data(), raw_u.data(),
