@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Benchmark: colourings/s of the batched FP32 (per-column scaled) count of
+"""Benchmark: colourings/s of the FP32 (per-column scaled) count of
 the 15-vertex complete binary tree on an RMAT graph with 2^20 vertices and
 200,000,000 directed edges (k = 15, 4 colourings per step), next to the plain
 one-colouring-per-pass FP64 path and the CPU oracle.
@@ -236,18 +236,45 @@ def adjoint_workload(sg, gg, torch, reps=2):
             "entries": G.nnz}
 
 
+def host_facts():
+    """CPU model and memory of the host, from /proc."""
+    model, mem_gb = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    mem_gb = int(line.split()[1]) / (1 << 20)
+                    break
+    except OSError:
+        pass
+    return model, mem_gb
+
+
 def cpu_baseline(parent, k, scale, seed, full_n, full_nnz):
-    """The oracle (FP64, OpenMP over vertices) on a bounded sample: the same
-    template and colouring rule on an RMAT graph of 2^scale vertices with the
-    full graph's average degree; scaled to the full graph by the oracle's
-    inner-loop count."""
+    """The oracle (FP64, OpenMP over vertices) on a bounded sample: one
+    colouring of the same template and colouring rule on an RMAT graph of
+    2^scale vertices with the full graph's average degree, timed here; the
+    rate is scaled to the full graph by the oracle's inner-loop count."""
     import graphgen as gg
     import oracle as O
 
     avg = full_nnz / full_n
     m = int(round(avg / 2 * (1 << scale)))
+    model, mem_gb = host_facts()
+    # the oracle's FP64 tables: about 40 GB at scale 18 (measured 5 GB at scale 15)
+    need_gb = 5.0 * (1 << scale) / (1 << 15)
+    while mem_gb is not None and scale > 14 and need_gb > 0.6 * mem_gb:
+        scale -= 1
+        m = int(round(avg / 2 * (1 << scale)))
+        need_gb /= 2
     G = gg.rmat(scale, m, seed=seed)
     col = O.colors(G.n, k, seed, 0)
+    log(f"cpu baseline: oracle on RMAT scale {scale} (n={G.n}, nnz={G.nnz}), {O.num_threads()} threads")
     t0 = time.perf_counter()
     O.count(G, parent, k, col)
     dt = time.perf_counter() - t0
@@ -257,9 +284,15 @@ def cpu_baseline(parent, k, scale, seed, full_n, full_nnz):
         "unit": "colorings/s",
         "cores": O.num_threads(),
         "kind": "oracle",
-        "sample": (f"1 colouring of bintree15 (k={k}) on RMAT scale {scale} "
-                   f"(n={G.n}, nnz={G.nnz}, same average degree) took {dt:.2f} s; scaled by the "
-                   f"oracle's inner-loop count to the full graph (x{ratio:.1f})"),
+        "sample": (f"measured: 1 colouring of bintree15 (k={k}, FP64) on RMAT scale {scale} "
+                   f"(n={G.n}, nnz={G.nnz}, the full graph's average degree) took {dt:.1f} s on "
+                   f"{O.num_threads()} threads; value = that rate scaled by the oracle's "
+                   f"inner-loop count to the full graph (x{ratio:.2f})"),
+        "sample_seconds": dt,
+        "sample_colorings_per_s": 1.0 / dt,
+        "sample_scale": scale,
+        "host_cpu": model,
+        "host_mem_gb": mem_gb,
     }
 
 
@@ -273,7 +306,7 @@ def main():
     ap.add_argument("--edges", type=int, default=100_000_000, help="undirected edges")
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-scale", type=int, default=14)
+    ap.add_argument("--cpu-scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch-workload", action="store_true",
@@ -369,6 +402,8 @@ def main():
         log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, fp32s rel err {err:.2e}")
 
     sp = prof["spmm"]
+    # one neighbour-colour histogram per pass (bintree15 has one single-vertex passive child)
+    passes = prof["hist"]["launches"] // args.steps if args.steps else 0
     achieved = sp["bytes"] / (sp["ms"] * 1e-3) / 1e9 if sp["ms"] > 0 else 0.0
     # measured HBM bytes per SpMM launch (rocprofv3 counters)
     traffic = load_traffic(sp["launches"] // (args.steps * ncol) if sp["launches"] % (args.steps * ncol) == 0
@@ -395,7 +430,14 @@ def main():
             "graph": {"generator": "rmat", "scale": args.scale, "a_b_c": list(gg.RMAT_ABC),
                       "n": G.n, "nnz": G.nnz, "seed": args.seed},
             "template": "bintree15", "k": k, "colorings_per_step": ncol,
-            "mode": "fp32 mantissa + per-column exponent, colourings batched",
+            "passes_per_step": passes,
+            "colorings_per_pass": ncol / passes if passes else None,
+            "mode": ("fp32 mantissa + per-column exponent; one colouring per pass (a single "
+                     "colouring's 6435-column table already fills 101 SpMM column chunks, so "
+                     "colourings are not concatenated as columns here)"
+                     if passes == ncol else
+                     f"fp32 mantissa + per-column exponent; {ncol // max(passes, 1)} colourings "
+                     "concatenated as table columns per pass"),
         },
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,

@@ -185,8 +185,13 @@ sg2v_status sg2v_colorings_download(const sg2v_colorings *c, uint8_t *out, void 
  * colorful_u64 (nullable): the exact count modulo 2^64, SG2V_U64 mode only.
  * overflow (nullable): set to 1 if a U64 intermediate exceeded 2^64 - 1.
  * All output pointers are host pointers with n_colorings entries (nullable).
- * Colourings are processed in batches: several colourings become extra
- * columns of the same tables so that each pass over A_G serves all of them.
+ * Colourings are processed in passes of b colourings that sit side by side
+ * as extra columns of the same tables (column j * C(k, m) + I_C), so that one
+ * SpMM launch over A_G serves all b of them; b = 1024 / (columns of the
+ * widest aggregated table), at least 1 (the tuning's batch overrides it) and
+ * halved until the pass fits the device memory.  Tables of 1024 or more
+ * columns run one colouring per pass: their column chunks each hold one
+ * colouring's columns.
  * Errors: EINVAL (k of c differs from the plan's, U64 with weights),
  *         ENOMEM, EDEVICE. */
 sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
