@@ -81,6 +81,35 @@ const char *sg2v_version(void);
 sg2v_status sg2v_plan_create(const int32_t *parent, int32_t t, int32_t k, sg2v_plan **out);
 void sg2v_plan_destroy(sg2v_plan *plan);
 
+/* Several templates over the same k colours in one plan, for one count of
+ * all of them (a treelet distribution, Sec. 2.1).  Rooted sub-templates that
+ * are isomorphic are shared across the templates, keyed by their canonical
+ * form, so each is aggregated and combined once per colouring.
+ *   parents     : host, the parent arrays of the templates one after another
+ *                 (sum of sizes entries), each as for sg2v_plan_create.
+ *   sizes       : host, n_templates vertex counts, 1 <= sizes[r] <= k.
+ * No template may be the same rooted tree as another or a rooted
+ * sub-template of another (EINVAL); templates of equal size never are unless
+ * they repeat.  Such a plan is counted with sg2v_count_multi; sg2v_count,
+ * sg2v_count_batch, sg2v_count_grad and sg2v_autotune reject it.
+ * sg2v_plan_info describes its first template (n_templates gives the number).
+ * Errors: EINVAL, ENOTTREE, ERANGE. */
+sg2v_status sg2v_plan_create_multi(const int32_t *parents, const int32_t *sizes,
+                                   int32_t n_templates, int32_t k, sg2v_plan **out);
+
+/* The non-isomorphic (free, unlabelled) trees with t vertices, the template
+ * set of a treelet distribution (Sec. 2.1: 47 trees of nine vertices).  Host
+ * only; grown one vertex at a time, duplicates removed by the centre-rooted
+ * canonical form.  Trees come in increasing order of that form; each parent
+ * array has root 0 at a centre and vertices numbered breadth first.
+ *   t          : 1 <= t <= SG2V_KMAX (t = 20 has 823,065 trees and takes
+ *                seconds).
+ *   max_trees  : parent arrays to write (0: count only).
+ *   parents_out: host, max_trees * t int32 (nullable when max_trees = 0).
+ *   n_trees    : the number of trees.
+ * Errors: EINVAL, ERANGE. */
+sg2v_status sg2v_trees(int32_t t, int64_t max_trees, int32_t *parents_out, int64_t *n_trees);
+
 /* An isomorphic copy of T whose decomposition (Sec. 2.3.2) costs less; host
  * only.  The colourful count sums rooted counts over every image of the root,
  * so it is the number of colourful injective maps of T: it depends neither on
@@ -115,6 +144,11 @@ typedef struct {
   int64_t spmm_columns;   /* sum over distinct passives of C(k, |T_p|) */
   int64_t pairs_per_vertex; /* sum over splits of C(k,|T_s|) C(|T_s|,|T_a|) */
   int64_t widest_table;   /* max over nodes of C(k, |T_s|) */
+  int32_t n_templates;    /* templates of the plan (sg2v_plan_create_multi), else 1 */
+  int32_t reserved;
+  int64_t bytes_per_vertex_fp32; /* device memory of one colouring's pass per graph vertex,
+                                    FP32S tables (liveness-packed), with automatic settings */
+  int64_t bytes_per_vertex_fp64; /* the same with FP64 or U64 tables */
 } sg2v_plan_info_t;
 
 sg2v_status sg2v_plan_info(const sg2v_plan *plan, sg2v_plan_info_t *out);
@@ -219,6 +253,58 @@ sg2v_status sg2v_count_noalloc(const sg2v_plan *plan, const sg2v_graph *g,
                                const sg2v_colorings *c, sg2v_mode mode, void *stream,
                                double *colorful, uint64_t *colorful_u64, double *estimate,
                                double *mean_estimate, int32_t *overflow);
+
+/* Counts of every template of a plan (sg2v_plan_create_multi, or any plan)
+ * over the colourings of c, in one dynamic programme whose shared
+ * sub-template tables are computed once per colouring.
+ *   colorful, colorful_u64, estimate : n_templates x n_colorings, template-major.
+ *   mean_estimate : n_templates, the average estimate of each template.
+ *   frequency     : n_templates, mean_estimate normalised to sum 1 (the
+ *                   treelet distribution; all zero if every mean is zero).
+ * All host pointers are nullable.  Errors as sg2v_count. */
+sg2v_status sg2v_count_multi(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
+                             sg2v_mode mode, void *stream, double *colorful,
+                             uint64_t *colorful_u64, double *estimate, double *mean_estimate,
+                             double *frequency, int32_t *overflow);
+
+/* (eps, delta) driver of the estimator (Alg. 1; Sec. 2.2.2 on the error
+ * guarantee): runs N colourings, N fixed by the median-of-means form of the
+ * bound N = O(e^k log(1/delta) / eps^2) that Alg. 1 states without constant:
+ * r = ceil(8 ln(1/delta)) groups of m = ceil(4 (1/P - 1) / eps^2) colourings
+ * (a per-colouring estimate lies in [0, emb/P], so its variance is at most
+ * emb^2 (1/P - 1)); the median of the group means is within eps * emb with
+ * probability at least 1 - delta.  Colourings are j = 0 .. N-1 of `seed`
+ * (sg2v_color), counted with sg2v_count in `mode` on a graph with
+ * non-negative weights.
+ *   max_colorings : cap on N (0: 2^24 - 1); a smaller cap keeps r groups.
+ *   flags         : SG2V_ESTIMATE_ADAPTIVE stops after a group once the
+ *                   normal-approximation interval of the mean at level
+ *                   1 - delta is within eps of the mean (at least 2 groups).
+ *   out           : results (below).
+ *   trace         : nullable, host, r doubles: the running mean after each
+ *                   group (convergence report).
+ * Errors: EINVAL (bad eps, delta or flags), ERANGE (cap >= 2^24), those of
+ * sg2v_color and sg2v_count. */
+#define SG2V_ESTIMATE_ADAPTIVE 1u
+typedef struct {
+  int64_t n_colorings;   /* colourings counted */
+  int64_t n_bound;       /* r * m from (eps, delta) */
+  int64_t group_size;    /* colourings per group */
+  int32_t groups;        /* groups counted */
+  int32_t stopped_early; /* adaptive stop */
+  int32_t capped;        /* max_colorings was below n_bound */
+  int32_t reserved;
+  double mean;           /* average estimate (Alg. 1's output) */
+  double median_of_means;
+  double variance;       /* sample variance of the per-colouring estimates */
+  double std_error;      /* sqrt(variance / n_colorings) */
+  double ci_low, ci_high;   /* mean -+ z std_error, z the two-sided normal quantile of delta */
+  double rel_half_width;    /* z std_error / mean */
+} sg2v_estimate_t;
+
+sg2v_status sg2v_estimate(const sg2v_plan *plan, const sg2v_graph *g, uint64_t seed, double eps,
+                          double delta, sg2v_mode mode, int64_t max_colorings, uint32_t flags,
+                          void *stream, sg2v_estimate_t *out, double *trace);
 
 /* Several templates over n_colorings colourings each (colourings
  * seed-derived per plan: sg2v_color(g, k_p, seed, 0, n_colorings)), run as

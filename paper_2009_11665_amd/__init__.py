@@ -46,7 +46,19 @@ class PlanInfo(ctypes.Structure):
                 ("n_splits", ctypes.c_int32), ("n_passive", ctypes.c_int32),
                 ("root_node", ctypes.c_int32), ("alpha", ctypes.c_int64),
                 ("colorful_prob", ctypes.c_double), ("spmm_columns", ctypes.c_int64),
-                ("pairs_per_vertex", ctypes.c_int64), ("widest_table", ctypes.c_int64)]
+                ("pairs_per_vertex", ctypes.c_int64), ("widest_table", ctypes.c_int64),
+                ("n_templates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bytes_per_vertex_fp32", ctypes.c_int64), ("bytes_per_vertex_fp64", ctypes.c_int64)]
+
+
+class EstimateResult(ctypes.Structure):
+    _fields_ = [("n_colorings", ctypes.c_int64), ("n_bound", ctypes.c_int64),
+                ("group_size", ctypes.c_int64), ("groups", ctypes.c_int32),
+                ("stopped_early", ctypes.c_int32), ("capped", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("mean", ctypes.c_double),
+                ("median_of_means", ctypes.c_double), ("variance", ctypes.c_double),
+                ("std_error", ctypes.c_double), ("ci_low", ctypes.c_double),
+                ("ci_high", ctypes.c_double), ("rel_half_width", ctypes.c_double)]
 
 
 class NodeInfo(ctypes.Structure):
@@ -68,7 +80,8 @@ EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_des
            "sg2v_color", "sg2v_colorings_destroy", "sg2v_colorings_download", "sg2v_count",
            "sg2v_count_batch", "sg2v_count_grad", "sg2v_debug_table", "sg2v_set_tuning",
            "sg2v_get_tuning", "sg2v_profile_start", "sg2v_profile_stop", "sg2v_autotune",
-           "sg2v_count_noalloc"]
+           "sg2v_count_noalloc", "sg2v_plan_create_multi", "sg2v_trees", "sg2v_count_multi",
+           "sg2v_estimate"]
 
 KERNEL_KINDS = ["color", "hist", "spmm", "spmm_combine", "ema_general", "ema_single", "root"]
 
@@ -113,6 +126,11 @@ def lib():
         L.sg2v_colorings_download.argtypes = [P, P, P]
         L.sg2v_count.argtypes = [P, P, P, i32, P, P, P, P, P, P]
         L.sg2v_count_noalloc.argtypes = [P, P, P, i32, P, P, P, P, P, P]
+        L.sg2v_plan_create_multi.argtypes = [P, P, i32, i32, ctypes.POINTER(P)]
+        L.sg2v_trees.argtypes = [i32, i64, P, ctypes.POINTER(ctypes.c_int64)]
+        L.sg2v_count_multi.argtypes = [P, P, P, i32, P, P, P, P, P, P, P]
+        L.sg2v_estimate.argtypes = [P, P, u64, ctypes.c_double, ctypes.c_double, i32, i64, u32, P,
+                                    ctypes.POINTER(EstimateResult), P]
         L.sg2v_count_batch.argtypes = [P, i32, P, u64, i32, i32, P, P, P]
         L.sg2v_count_grad.argtypes = [P, P, P, i32, P, P, P]
         L.sg2v_debug_table.argtypes = [P, P, P, i32, i32, i32, i32, P, P]
@@ -168,6 +186,15 @@ def reroot(parent: Sequence[int], k: Optional[int] = None, spmm_weight: float = 
     return [int(x) for x in out], [int(x) for x in perm]
 
 
+def trees(t: int):
+    """The non-isomorphic trees with t vertices as parent arrays (sg2v_trees)."""
+    n = ctypes.c_int64(0)
+    _check(lib().sg2v_trees(int(t), 0, None, ctypes.byref(n)), "sg2v_trees")
+    out = np.zeros((n.value, int(t)), np.int32)
+    _check(lib().sg2v_trees(int(t), n.value, _ptr(out), ctypes.byref(n)), "sg2v_trees")
+    return [[int(x) for x in row] for row in out]
+
+
 class Plan:
     """sg2v_plan: template partition, split tables, alpha and P."""
 
@@ -176,10 +203,29 @@ class Plan:
         self.parent = [int(x) for x in par]
         self.t = len(par)
         self.k = self.t if k is None else int(k)
+        self.n_templates = 1
         h = ctypes.c_void_p()
         _check(lib().sg2v_plan_create(_ptr(par), self.t, self.k, ctypes.byref(h)),
                "sg2v_plan_create")
         self.h = h
+
+    @classmethod
+    def multi(cls, parents: Sequence[Sequence[int]], k: Optional[int] = None):
+        """One plan of several templates sharing isomorphic sub-templates
+        (sg2v_plan_create_multi); count it with count_multi()."""
+        sizes = np.ascontiguousarray([len(p) for p in parents], np.int32)
+        flat = np.ascontiguousarray([int(x) for p in parents for x in p], np.int32)
+        self = cls.__new__(cls)
+        self.parent = [int(x) for x in parents[0]]
+        self.parents = [[int(x) for x in p] for p in parents]
+        self.t = len(parents[0])
+        self.k = max(len(p) for p in parents) if k is None else int(k)
+        self.n_templates = len(parents)
+        h = ctypes.c_void_p()
+        _check(lib().sg2v_plan_create_multi(_ptr(flat), _ptr(sizes), len(parents), self.k,
+                                            ctypes.byref(h)), "sg2v_plan_create_multi")
+        self.h = h
+        return self
 
     def info(self) -> PlanInfo:
         i = PlanInfo()
@@ -291,6 +337,42 @@ def count(plan: Plan, graph: Graph, col: Colorings, mode="fp32s", stream=None):
                             _ptr(est), ctypes.byref(mean), ctypes.byref(ovf)), "sg2v_count")
     return dict(colorful=cf, colorful_u64=cu, estimate=est, mean_estimate=mean.value,
                 overflow=bool(ovf.value))
+
+
+def count_multi(plan: Plan, graph: Graph, col: Colorings, mode="fp32s", stream=None):
+    """Every template of a plan (sg2v_count_multi).  Returns dict(colorful,
+    colorful_u64, estimate: [n_templates, n_colorings]; mean_estimate,
+    frequency: [n_templates]; overflow)."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    r, n = plan.n_templates, col.count
+    cf = np.zeros((r, n), np.float64)
+    cu = np.zeros((r, n), np.uint64)
+    est = np.zeros((r, n), np.float64)
+    mean = np.zeros(r, np.float64)
+    freq = np.zeros(r, np.float64)
+    ovf = ctypes.c_int32(0)
+    _check(lib().sg2v_count_multi(plan.h, graph.h, col.h, m, _stream(stream), _ptr(cf), _ptr(cu),
+                                  _ptr(est), _ptr(mean), _ptr(freq), ctypes.byref(ovf)),
+           "sg2v_count_multi")
+    return dict(colorful=cf, colorful_u64=cu, estimate=est, mean_estimate=mean, frequency=freq,
+                overflow=bool(ovf.value))
+
+
+ESTIMATE_ADAPTIVE = 1
+
+
+def estimate(plan: Plan, graph: Graph, seed: int, eps: float, delta: float, mode="fp64",
+             max_colorings: int = 0, adaptive: bool = False, stream=None):
+    """(eps, delta) estimate of the number of copies (sg2v_estimate).
+    Returns (EstimateResult, trace of running means per group)."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    out = EstimateResult()
+    groups = max(1, int(np.ceil(8.0 * np.log(1.0 / delta))))
+    trace = np.zeros(groups, np.float64)
+    _check(lib().sg2v_estimate(plan.h, graph.h, int(seed), float(eps), float(delta), m,
+                               int(max_colorings), ESTIMATE_ADAPTIVE if adaptive else 0,
+                               _stream(stream), ctypes.byref(out), _ptr(trace)), "sg2v_estimate")
+    return out, trace[:out.groups]
 
 
 def count_noalloc(plan: Plan, graph: Graph, col: Colorings, mode="fp32s", stream=None):

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsg2v.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "kernels.hip", "runtime.hip"]
+SOURCES = ["plan.cpp", "trees.cpp", "estimate.cpp", "kernels.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SG2V_ARCH", "gfx950")
 

@@ -68,7 +68,24 @@ enum RootKind {
   ROOT_VERTEX = 3,   // the template is one vertex
 };
 
+// Root reduction of one template of a plan.
+struct RootInfo {
+  int node = -1;               // node id of the template itself
+  int t = 0;                   // template vertices
+  int kind = ROOT_VERTEX;
+  int x_node = -1, y_node = -1;
+  int64_t L = 0;
+  std::vector<int32_t> list;   // [k][L] x (x, y)
+  int64_t alpha = 1;           // |Aut(T)|
+  double P = 1.0;              // colourful probability
+  std::vector<int32_t> parent; // the template as given
+};
+
 struct Plan {
+  // The first (or only) template: t, parent, root, alpha, P and the root_*
+  // fields below describe it.  A plan of several templates (treelet
+  // distributions) shares its sub-template nodes across them and keeps one
+  // RootInfo per template in `roots`.
   int t = 0, k = 0;
   std::vector<int32_t> parent;
   std::vector<Node> nodes;
@@ -84,6 +101,8 @@ struct Plan {
   std::vector<int32_t> root_list;  // [k][L] x (x, y)
   // nodes whose tables are never materialised (fused into the root)
   std::vector<char> fused;
+  std::vector<RootInfo> roots;   // one per template, roots[0] = the fields above
+  std::vector<int> root_index;   // per node: index into roots, or -1
 
   // device copies of the tables, uploaded on first use per device
   struct DeviceTables {
@@ -91,8 +110,8 @@ struct Plan {
     std::vector<void *> pairs, drop;  // per node
     std::vector<void *> tr_a, tr_p, add;
     std::vector<void *> cpr;  // colour-restricted tables, one block per node
-    void *root_list = nullptr;
-    void *root_list16 = nullptr;  // (x | y << 16), when every index fits 16 bits
+    std::vector<void *> root_list;    // per template
+    std::vector<void *> root_list16;  // (x | y << 16), when every index fits 16 bits
     // SpMM colour-skip masks per (node, colourings per pass, chunk width)
     std::map<std::tuple<int, int, int>, void *> chunks;
   };
@@ -101,6 +120,13 @@ struct Plan {
 };
 
 sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out);
+// Several templates over the same k, sharing isomorphic rooted sub-templates.
+sg2v_status plan_build_multi(const int32_t *const *parents, const int32_t *ts, int n, int k,
+                             Plan &out);
+// Device workspace of one pass over one colouring, per vertex (runtime).
+int64_t pass_bytes_per_vertex(const Plan &P, int fp32);
+// Vertices of a registered graph (runtime).
+int64_t graph_vertices(const sg2v_graph *g);
 
 }  // namespace sg2v
 

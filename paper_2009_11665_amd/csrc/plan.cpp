@@ -196,46 +196,88 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
     set_error("sg2v_plan_create: parent is NULL");
     return SG2V_EINVAL;
   }
-  if (t < 1 || k < t || k > SG2V_KMAX) {
-    set_error("sg2v_plan_create: need 1 <= t <= k <= %d (t=%d, k=%d)", SG2V_KMAX, t, k);
-    return SG2V_ERANGE;
+  const int32_t *ps[1] = {parent};
+  const int32_t ts[1] = {t};
+  return plan_build_multi(ps, ts, 1, k, out);
+}
+
+sg2v_status plan_build_multi(const int32_t *const *parents, const int32_t *ts, int n_templates,
+                             int k, Plan &out) {
+  if (!parents || !ts || n_templates < 1) {
+    set_error("sg2v_plan_create: null template list or no template");
+    return SG2V_EINVAL;
   }
-  Tree T;
-  sg2v_status st = tree_from_parent(parent, t, T);
-  if (st != SG2V_OK) return st;
+  std::vector<Tree> trees(n_templates);
+  for (int r = 0; r < n_templates; ++r) {
+    const int t = ts[r];
+    if (!parents[r]) {
+      set_error("sg2v_plan_create: parent of template %d is NULL", r);
+      return SG2V_EINVAL;
+    }
+    if (t < 1 || k < t || k > SG2V_KMAX) {
+      set_error("sg2v_plan_create: need 1 <= t <= k <= %d (template %d: t=%d, k=%d)", SG2V_KMAX, r,
+                t, k);
+      return SG2V_ERANGE;
+    }
+    sg2v_status st = tree_from_parent(parents[r], t, trees[r]);
+    if (st != SG2V_OK) return st;
+  }
   Plan *P = &out;
-  P->t = t;
+  P->t = ts[0];
   P->k = k;
-  P->parent.assign(parent, parent + t);
+  P->parent.assign(parents[0], parents[0] + ts[0]);
 
   // Partition: node (v, n_kept) = v with its first n_kept children's subtrees.
   // Cut the edge to the last kept child: active = (v, n_kept - 1), passive =
-  // (child, all its children).  Nodes are emitted after their children.
+  // (child, all its children).  Nodes are emitted after their children; a
+  // rooted sub-template met again (in this template or an earlier one) reuses
+  // the first node with its canonical form.
   std::map<std::string, int> by_canon;
-  std::function<int(int, int)> build = [&](int v, int n_kept) -> int {
-    std::string key = kept_canon(T, v, n_kept);
-    auto it = by_canon.find(key);
-    if (it != by_canon.end()) return it->second;
-    Node nd;
-    nd.vertex = v;
-    nd.n_kept = n_kept;
-    nd.canon = key;
-    if (n_kept > 0) {
-      int tau = T.ch[v][n_kept - 1];
-      nd.active = build(v, n_kept - 1);
-      nd.passive = build(tau, (int)T.ch[tau].size());
-      nd.size = P->nodes[nd.active].size + P->nodes[nd.passive].size;
-    }
-    nd.cols = binom(k, nd.size);
-    P->nodes.push_back(nd);
-    int id = (int)P->nodes.size() - 1;
-    by_canon[key] = id;
-    return id;
-  };
-  P->root = build(T.root, (int)T.ch[T.root].size());
+  P->roots.assign(n_templates, RootInfo());
+  for (int r = 0; r < n_templates; ++r) {
+    const Tree &T = trees[r];
+    std::function<int(int, int)> build = [&](int v, int n_kept) -> int {
+      std::string key = kept_canon(T, v, n_kept);
+      auto it = by_canon.find(key);
+      if (it != by_canon.end()) return it->second;
+      Node nd;
+      nd.vertex = v;
+      nd.n_kept = n_kept;
+      nd.canon = key;
+      if (n_kept > 0) {
+        int tau = T.ch[v][n_kept - 1];
+        nd.active = build(v, n_kept - 1);
+        nd.passive = build(tau, (int)T.ch[tau].size());
+        nd.size = P->nodes[nd.active].size + P->nodes[nd.passive].size;
+      }
+      nd.cols = binom(k, nd.size);
+      P->nodes.push_back(nd);
+      int id = (int)P->nodes.size() - 1;
+      by_canon[key] = id;
+      return id;
+    };
+    P->roots[r].node = build(T.root, (int)T.ch[T.root].size());
+    P->roots[r].t = ts[r];
+    P->roots[r].parent.assign(parents[r], parents[r] + ts[r]);
+  }
+  P->root = P->roots[0].node;
   for (auto &nd : P->nodes) {
     if (nd.active >= 0) P->nodes[nd.active].n_active_uses++;
     if (nd.passive >= 0) P->nodes[nd.passive].n_passive_uses++;
+  }
+  P->root_index.assign(P->nodes.size(), -1);
+  for (int r = 0; r < n_templates; ++r) {
+    const int nr = P->roots[r].node;
+    if (P->root_index[nr] >= 0) {
+      set_error("sg2v_plan_create: templates %d and %d are the same rooted tree",
+                P->root_index[nr], r);
+      return SG2V_EINVAL;
+    }
+    if (P->nodes[nr].n_active_uses || P->nodes[nr].n_passive_uses) {
+      set_error("sg2v_plan_create: template %d is a rooted sub-template of another template", r);
+      return SG2V_EINVAL;
+    }
+    P->root_index[nr] = r;
   }
 
   // Split tables: for each output set C (colex order), every subset S of C
@@ -314,7 +356,7 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
   // from its children's tables (root lists below) and gets none.
   for (size_t ni = 0; ni < P->nodes.size(); ++ni) {
     Node &nd = P->nodes[ni];
-    if (nd.size == 1 || (int)ni == P->root) continue;
+    if (nd.size == 1 || P->root_index[ni] >= 0) continue;
     const Node &A = P->nodes[nd.active];
     const Node &Pn = P->nodes[nd.passive];
     if (A.size == 1) continue;
@@ -380,62 +422,75 @@ sg2v_status plan_build(const int32_t *parent, int t, int k, Plan &out) {
     }
   }
 
-  // Root reduction lists.
+  // Root reduction lists, one per template.
   P->fused.assign(P->nodes.size(), 0);
-  const Node &R = P->nodes[P->root];
-  if (R.size == 1) {
-    P->root_kind = ROOT_VERTEX;
-  } else {
-    const Node &A = P->nodes[R.active];
-    P->root_y_node = R.passive;
-    std::vector<std::vector<int32_t>> lists(k);
-    int64_t nout = binom(k, t);
-    if (A.size == 1) {
-      P->root_kind = ROOT_SINGLE;
-      P->root_x_node = R.passive;
-      P->root_y_node = -1;
-      for (int64_t r = 0; r < nout; ++r) {
-        uint32_t C = colex_unrank(r, t, k);
-        for (int c = 0; c < k; ++c)
-          if (C >> c & 1u) {
-            lists[c].push_back((int32_t)colex_rank(C & ~(1u << c)));
-            lists[c].push_back(-1);
-          }
-      }
+  for (int ri = 0; ri < n_templates; ++ri) {
+    RootInfo &RI = P->roots[ri];
+    const int t = RI.t;
+    const Node &R = P->nodes[RI.node];
+    if (R.size == 1) {
+      RI.kind = ROOT_VERTEX;
     } else {
-      bool fuse = P->nodes[A.active].size == 1 && A.n_active_uses == 1 && A.n_passive_uses == 0;
-      P->root_kind = fuse ? ROOT_FUSED : ROOT_GENERAL;
-      P->root_x_node = fuse ? A.passive : R.active;
-      if (fuse) P->fused[R.active] = 1;
-      std::vector<uint32_t> amask(binom(k, A.size));
-      for (size_t x = 0; x < amask.size(); ++x) amask[x] = colex_unrank((int64_t)x, A.size, k);
-      for (int64_t r = 0; r < nout; ++r) {
-        for (int q = 0; q < R.np; ++q) {
-          int32_t ia = R.pairs[((size_t)r * R.np + q) * 2 + 0];
-          int32_t ip = R.pairs[((size_t)r * R.np + q) * 2 + 1];
-          uint32_t S = amask[ia];
+      const Node &A = P->nodes[R.active];
+      RI.y_node = R.passive;
+      std::vector<std::vector<int32_t>> lists(k);
+      int64_t nout = binom(k, t);
+      if (A.size == 1) {
+        RI.kind = ROOT_SINGLE;
+        RI.x_node = R.passive;
+        RI.y_node = -1;
+        for (int64_t r = 0; r < nout; ++r) {
+          uint32_t C = colex_unrank(r, t, k);
           for (int c = 0; c < k; ++c)
-            if (S >> c & 1u) {
-              lists[c].push_back(fuse ? (int32_t)colex_rank(S & ~(1u << c)) : ia);
-              lists[c].push_back(ip);
+            if (C >> c & 1u) {
+              lists[c].push_back((int32_t)colex_rank(C & ~(1u << c)));
+              lists[c].push_back(-1);
             }
         }
+      } else {
+        // fused: the active child is a one-vertex-active split used only here
+        bool fuse = P->nodes[A.active].size == 1 && A.n_active_uses == 1 && A.n_passive_uses == 0;
+        RI.kind = fuse ? ROOT_FUSED : ROOT_GENERAL;
+        RI.x_node = fuse ? A.passive : R.active;
+        if (fuse) P->fused[R.active] = 1;
+        std::vector<uint32_t> amask(binom(k, A.size));
+        for (size_t x = 0; x < amask.size(); ++x) amask[x] = colex_unrank((int64_t)x, A.size, k);
+        for (int64_t r = 0; r < nout; ++r) {
+          for (int q = 0; q < R.np; ++q) {
+            int32_t ia = R.pairs[((size_t)r * R.np + q) * 2 + 0];
+            int32_t ip = R.pairs[((size_t)r * R.np + q) * 2 + 1];
+            uint32_t S = amask[ia];
+            for (int c = 0; c < k; ++c)
+              if (S >> c & 1u) {
+                lists[c].push_back(fuse ? (int32_t)colex_rank(S & ~(1u << c)) : ia);
+                lists[c].push_back(ip);
+              }
+          }
+        }
+      }
+      RI.L = (int64_t)lists[0].size() / 2;
+      RI.list.resize((size_t)k * RI.L * 2);
+      for (int c = 0; c < k; ++c) {
+        if ((int64_t)lists[c].size() != 2 * RI.L) {
+          set_error("sg2v_plan_create: internal error (root list sizes differ)");
+          return SG2V_EINVAL;
+        }
+        std::copy(lists[c].begin(), lists[c].end(), RI.list.begin() + (size_t)c * RI.L * 2);
       }
     }
-    P->root_L = (int64_t)lists[0].size() / 2;
-    P->root_list.resize((size_t)k * P->root_L * 2);
-    for (int c = 0; c < k; ++c) {
-      if ((int64_t)lists[c].size() != 2 * P->root_L) {
-        set_error("sg2v_plan_create: internal error (root list sizes differ)");
-        return SG2V_EINVAL;
-      }
-      std::copy(lists[c].begin(), lists[c].end(), P->root_list.begin() + (size_t)c * P->root_L * 2);
-    }
+    RI.alpha = tree_automorphisms(RI.parent.data(), t);
+    double p = 1.0;
+    for (int i = 0; i < t; ++i) p *= (double)(k - i) / (double)k;
+    RI.P = p;
   }
-  P->alpha = tree_automorphisms(parent, t);
-  double p = 1.0;
-  for (int i = 0; i < t; ++i) p *= (double)(k - i) / (double)k;
-  P->P = p;
+  const RootInfo &R0 = P->roots[0];
+  P->root_kind = R0.kind;
+  P->root_x_node = R0.x_node;
+  P->root_y_node = R0.y_node;
+  P->root_L = R0.L;
+  P->root_list = R0.list;
+  P->alpha = R0.alpha;
+  P->P = R0.P;
   return SG2V_OK;
 }
 
@@ -674,6 +729,38 @@ sg2v_status sg2v_plan_create(const int32_t *parent, int32_t t, int32_t k, sg2v_p
   }
 }
 
+sg2v_status sg2v_plan_create_multi(const int32_t *parents, const int32_t *sizes,
+                                   int32_t n_templates, int32_t k, sg2v_plan **out) {
+  if (!out || !parents || !sizes || n_templates < 1) {
+    set_error("sg2v_plan_create_multi: null argument or no template");
+    return SG2V_EINVAL;
+  }
+  *out = nullptr;
+  try {
+    std::vector<const int32_t *> ps(n_templates);
+    int64_t off = 0;
+    for (int r = 0; r < n_templates; ++r) {
+      if (sizes[r] < 1 || sizes[r] > SG2V_KMAX) {
+        set_error("sg2v_plan_create_multi: template %d has %d vertices", r, sizes[r]);
+        return SG2V_ERANGE;
+      }
+      ps[r] = parents + off;
+      off += sizes[r];
+    }
+    sg2v_plan *h = new sg2v_plan;
+    sg2v_status st = plan_build_multi(ps.data(), sizes, n_templates, k, h->p);
+    if (st != SG2V_OK) {
+      delete h;
+      return st;
+    }
+    *out = h;
+    return SG2V_OK;
+  } catch (const std::bad_alloc &) {
+    set_error("sg2v_plan_create_multi: out of host memory");
+    return SG2V_ENOMEM;
+  }
+}
+
 sg2v_status sg2v_template_reroot(const int32_t *parent, int32_t t, int32_t k, double spmm_weight,
                                  int32_t *parent_out, int32_t *perm_out) {
   try {
@@ -697,6 +784,9 @@ sg2v_status sg2v_plan_info(const sg2v_plan *plan, sg2v_plan_info_t *out) {
   out->root_node = P.root;
   out->alpha = P.alpha;
   out->colorful_prob = P.P;
+  out->n_templates = (int32_t)P.roots.size();
+  out->bytes_per_vertex_fp32 = pass_bytes_per_vertex(P, 1);
+  out->bytes_per_vertex_fp64 = pass_bytes_per_vertex(P, 0);
   for (auto &nd : P.nodes) {
     if (nd.size > 1) {
       out->n_splits++;

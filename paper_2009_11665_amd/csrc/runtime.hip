@@ -542,8 +542,8 @@ namespace {
 struct DevPlan {
   std::vector<int32_t *> pairs, drop;  // per node, device
   std::vector<int32_t *> tr_a, tr_p, add;
-  int32_t *root_list = nullptr;
-  uint32_t *root_list16 = nullptr;
+  std::vector<int32_t *> root_list;     // per template
+  std::vector<uint32_t *> root_list16;
   std::vector<char *> cpr;  // colour-restricted tables per node
 };
 
@@ -573,8 +573,10 @@ void fill_devplan(const Plan::DeviceTables &d, DevPlan *out) {
     out->tr_p[i] = (int32_t *)d.tr_p[i];
     out->add[i] = (int32_t *)d.add[i];
   }
-  out->root_list = (int32_t *)d.root_list;
-  out->root_list16 = (uint32_t *)d.root_list16;
+  out->root_list.clear();
+  out->root_list16.clear();
+  for (void *p : d.root_list) out->root_list.push_back((int32_t *)p);
+  for (void *p : d.root_list16) out->root_list16.push_back((uint32_t *)p);
   out->cpr.assign(nn, nullptr);
   for (size_t i = 0; i < nn && i < d.cpr.size(); ++i) out->cpr[i] = (char *)d.cpr[i];
 }
@@ -624,16 +626,20 @@ sg2v_status plan_device(const Plan &P, int device, hipStream_t s, DevPlan *out) 
         blk[cu0 + (size_t)c * nd.cols + nd.co[(size_t)c * nd.c_u + u]] = (uint32_t)u;
     ST_TRY(upload(blk, &D.cpr[i], s));
   }
-  if (!P.root_list.empty()) {
-    ST_TRY(upload(P.root_list, &D.root_list, s));
+  D.root_list.assign(P.roots.size(), nullptr);
+  D.root_list16.assign(P.roots.size(), nullptr);
+  for (size_t r = 0; r < P.roots.size(); ++r) {
+    const std::vector<int32_t> &rl = P.roots[r].list;
+    if (rl.empty()) continue;
+    ST_TRY(upload(rl, &D.root_list[r], s));
     bool fits = true;
-    std::vector<uint32_t> l16(P.root_list.size() / 2);
+    std::vector<uint32_t> l16(rl.size() / 2);
     for (size_t q = 0; q < l16.size(); ++q) {
-      const int32_t x = P.root_list[2 * q], y = P.root_list[2 * q + 1];
+      const int32_t x = rl[2 * q], y = rl[2 * q + 1];
       fits &= x >= 0 && x < 0xFFFF && y >= -1 && y < 0xFFFF;
       l16[q] = (uint32_t)x | ((uint32_t)(y < 0 ? 0xFFFF : y) << 16);
     }
-    if (fits) ST_TRY(upload(l16, &D.root_list16, s));
+    if (fits) ST_TRY(upload(l16, &D.root_list16[r], s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   P.dev.push_back(D);
@@ -727,9 +733,9 @@ void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots,
   for (size_t s = 0; s < nn; ++s) {
     const Node &nd = P.nodes[s];
     if (nd.size == 1) continue;
-    const bool is_root = (int)s == P.root;
-    if (is_root) {
-      if (P.root_kind == ROOT_FUSED) needB(P.nodes[nd.active].passive);
+    const int ri = P.root_index[s];
+    if (ri >= 0) {
+      if (P.roots[ri].kind == ROOT_FUSED) needB(P.nodes[nd.active].passive);
       needB(nd.passive);
       pp.steps.push_back({S_ROOT, (int)s});
       continue;
@@ -756,8 +762,8 @@ void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots,
         touch(pp.M[nd.active], x); touch(pp.B[nd.passive], x); touch(pp.M[st.node], x);
         break;
       case S_ROOT:
-        if (P.root_kind == ROOT_FUSED) touch(pp.B[P.nodes[nd.active].passive], x);
-        if (P.root_kind == ROOT_GENERAL) touch(pp.M[nd.active], x);
+        if (P.roots[P.root_index[st.node]].kind == ROOT_FUSED) touch(pp.B[P.nodes[nd.active].passive], x);
+        if (P.roots[P.root_index[st.node]].kind == ROOT_GENERAL) touch(pp.M[nd.active], x);
         touch(pp.B[nd.passive], x);
         break;
     }
@@ -808,6 +814,25 @@ void build_pass(const Plan &P, int64_t n, int b, int dt, int G, int64_t n_slots,
   pp.small_bytes = small + 256;
 }
 
+}  // namespace
+
+namespace sg2v {
+int64_t graph_vertices(const sg2v_graph *g) { return g ? g->n : 0; }
+
+int64_t pass_bytes_per_vertex(const Plan &P, int fp32) {
+  const int dt = fp32 ? DT_F32 : DT_F64;
+  const int64_t n = (int64_t)1 << 20;
+  int64_t widest = 1;
+  for (auto &nd : P.nodes)
+    if (nd.n_passive_uses > 0) widest = std::max(widest, nd.size == 1 ? (int64_t)P.k : nd.cols);
+  PassPlan pp;
+  build_pass(P, n, 1, dt, pick_G(dt, widest, n), 0, pp, PassOpts());
+  return (pp.arena + n - 1) / n;
+}
+}  // namespace sg2v
+
+namespace {
+
 struct Ctx {
   const Plan *P;
   sg2v_graph *g;
@@ -824,6 +849,7 @@ struct Ctx {
   int bucket_b = 0;
   int nbr_j0 = -1;     // pass whose neighbour colours are in ws->nbrcol
   int nbr_b = 0;
+  int64_t res_stride = 0;  // results per template (plans of several templates)
   // sg2v_count_noalloc: colour-skip masks copied into the scratch area
   std::map<std::tuple<int, int, int>, void *> tmp_masks;
   std::vector<std::vector<uint32_t>> tmp_host;
@@ -1354,12 +1380,17 @@ namespace {
 sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const Plan &P = *x.P;
   const Node &nd = P.nodes[node];
+  const int ri = P.root_index[node];
+  const RootInfo &RI = P.roots[ri];
+  // template ri's results follow those of the templates before it
+  result = (char *)result + (size_t)ri * x.res_stride * 8;
+  Eout += (size_t)ri * x.res_stride;
   RootArgs a{};
   std::memset(&a, 0, sizeof(a));
   Tab *X = nullptr, *Y = nullptr;
-  if (P.root_kind == ROOT_SINGLE) {
+  if (RI.kind == ROOT_SINGLE) {
     X = &x.pp.B[nd.passive];
-  } else if (P.root_kind == ROOT_FUSED) {
+  } else if (RI.kind == ROOT_FUSED) {
     X = &x.pp.B[P.nodes[nd.active].passive];
     Y = &x.pp.B[nd.passive];
   } else {
@@ -1374,8 +1405,8 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
     a.ldy = Y->ld;
     a.Cy = (int32_t)Y->cols;
   }
-  a.list = x.dp.root_list;
-  a.L = P.root_L;
+  a.list = x.dp.root_list[ri];
+  a.L = RI.L;
   a.n = x.g->n;
   a.colors = x.c->d;
   a.j0 = x.j0;
@@ -1385,7 +1416,7 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   }
   a.partial = x.ws->partial.p;
   a.ovf = x.ovf;
-  a.list16 = x.dp.root_list16;
+  a.list16 = x.dp.root_list16[ri];
   a.same_xy = Y && Y->p == X->p;
   a.k = P.k;
   const size_t stage = (size_t)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es;
@@ -1397,15 +1428,15 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   const size_t tile_lds = (tile_db ? 2 : 1) * row_lds;
   const bool aligned = x.b == 1 || (X->cols * x.es) % 16 == 0;
   const bool use_tile = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && (!Y || a.same_xy) &&
-                        aligned && P.root_L <= 16 * 256 && X->cols <= 8192 && tile_lds <= 64 * 1024;
+                        aligned && RI.L <= 16 * 256 && X->cols <= 8192 && tile_lds <= 64 * 1024;
   // narrow rows and short lists: one thread per vertex
-  const bool use_thread = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && P.root_L <= 256 &&
-                          (int64_t)P.k * P.root_L <= 8192 && X->cols <= 512 && (!Y || Y->cols <= 512);
+  const bool use_thread = a.list16 && !(tuning().flags & SG2V_TUNE_ROOT_ROWS) && RI.L <= 256 &&
+                          (int64_t)P.k * RI.L <= 8192 && X->cols <= 512 && (!Y || Y->cols <= 512);
   // narrow rows: a tile of rows staged in LDS, a few lanes per vertex
   int stage_R = 0;
   size_t stage_lds = 0;
   if (use_thread && !(tuning().flags & SG2V_TUNE_ROOT_THREAD)) {
-    const size_t lists = (size_t)round_up((int64_t)P.k * P.root_L * 4, 16);
+    const size_t lists = (size_t)round_up((int64_t)P.k * RI.L * 4, 16);
     const size_t per_row = (size_t)(X->cols + (Y ? Y->cols : 0)) * x.es;
     for (int R = 64; R >= 4 && !stage_R; R /= 2)
       if (lists + R * per_row <= 48 * 1024) stage_R = R;
@@ -1422,7 +1453,7 @@ sg2v_status step_root(Ctx &x, int node, void *result, int *Eout) {
   {
     ProfScope ps(SG2V_K_ROOT,
                  (double)x.g->n * x.b * (double)(X->cols + (Y && !a.same_xy ? Y->cols : 0)) * x.es,
-                 (double)x.g->n * x.b * (double)P.root_L, x.s);
+                 (double)x.g->n * x.b * (double)RI.L, x.s);
     if (stage_R) launch_root_stage(x.dt, a, dim3(nblk, x.b), stage_R, stage_lds, x.s);
     else if (use_thread) launch_root_thread(x.dt, a, dim3(nblk, x.b), x.s);
     else if (use_tile) launch_root_tile(x.dt, a, dim3(nblk, x.b), tile_lds, tile_db, x.s);
@@ -1635,7 +1666,7 @@ sg2v_status enqueue_count(Ctx &x, int ncol, int b, void *res, int *Ed) {
   return SG2V_OK;
 }
 
-void finish_counts(const Plan &P, int ncol, int dt, const double *rf, const uint64_t *ru,
+void finish_counts(const RootInfo &P, int ncol, int dt, const double *rf, const uint64_t *ru,
                    const int *E, double *colorful, uint64_t *colorful_u64, double *estimate,
                    double *mean_estimate) {
   double mean = 0.0;
@@ -1653,47 +1684,117 @@ void finish_counts(const Plan &P, int ncol, int dt, const double *rf, const uint
 
 }  // namespace
 
+namespace {
+
+// Raw colourful sums of every template of the plan for every colouring of c:
+// rf / ru / E hold n_templates x ncol entries, template-major (FP32S sums
+// still to be scaled by 2^E).  Templates of one vertex are filled on the host.
+sg2v_status count_raw(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
+                      sg2v_mode mode, hipStream_t s, std::vector<double> &rf,
+                      std::vector<uint64_t> &ru, std::vector<int> &E, int *ovf_h) {
+  const Plan &P = plan->p;
+  const int ncol = c->count;
+  const int nr = (int)P.roots.size();
+  const int dt = dtype_of(mode);
+  rf.assign((size_t)nr * ncol, 0.0);
+  ru.assign((size_t)nr * ncol, 0);
+  E.assign((size_t)nr * ncol, 0);
+  *ovf_h = 0;
+  bool device = false;
+  for (auto &R : P.roots) device |= R.kind != ROOT_VERTEX;
+  if (device) {
+    const int b = choose_batch(P, ncol, dt, g->n, g->n_slots);
+    Ctx x;
+    ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, b, s, PassOpts()));
+    x.res_stride = ncol;
+    ST_TRY(prewarm(x, b));
+    ST_TRY(prewarm(x, ncol % b));
+    const size_t nres = (size_t)nr * ncol;
+    ST_TRY(x.ws->result.ensure(nres * 12 + 64));
+    void *res = x.ws->result.p;
+    int *Ed = (int *)((char *)res + nres * 8);
+    launch_fill_u32((unsigned *)x.ovf, 1, 0u, s);
+    ST_TRY(enqueue_count(x, ncol, b, res, Ed));
+    HIP_TRY(hipMemcpyAsync(dt == DT_U64 ? (void *)ru.data() : (void *)rf.data(), res, nres * 8,
+                           hipMemcpyDeviceToHost, s));
+    if (dt == DT_F32) HIP_TRY(hipMemcpyAsync(E.data(), Ed, nres * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ovf_h, x.ovf, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  // every vertex is one colourful map of a one-vertex template
+  for (int r = 0; r < nr; ++r)
+    if (P.roots[r].kind == ROOT_VERTEX)
+      for (int j = 0; j < ncol; ++j) {
+        rf[(size_t)r * ncol + j] = (double)g->n;
+        ru[(size_t)r * ncol + j] = (uint64_t)g->n;
+        E[(size_t)r * ncol + j] = 0;
+      }
+  return SG2V_OK;
+}
+
+// Scaled counts and estimates of template r (raw sums of a one-vertex
+// template are doubles whatever the mode).
+void finish_template(const Plan &P, int r, int ncol, int dt, const std::vector<double> &rf,
+                     const std::vector<uint64_t> &ru, const std::vector<int> &E, double *colorful,
+                     uint64_t *colorful_u64, double *estimate, double *mean_estimate) {
+  const RootInfo &R = P.roots[r];
+  const size_t o = (size_t)r * ncol;
+  const bool vertex = R.kind == ROOT_VERTEX;
+  finish_counts(R, ncol, vertex ? DT_F64 : dt, rf.data() + o, ru.data() + o, E.data() + o,
+                colorful, colorful_u64, estimate, mean_estimate);
+  if (colorful_u64 && vertex)
+    for (int j = 0; j < ncol; ++j) colorful_u64[j] = ru[o + j];
+}
+
+}  // namespace
+
 extern "C" sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g,
                                   const sg2v_colorings *c, sg2v_mode mode, void *stream,
                                   double *colorful, uint64_t *colorful_u64, double *estimate,
                                   double *mean_estimate, int32_t *overflow) {
   ST_TRY(check_inputs(plan, g, c, mode));
-  const Plan &P = plan->p;
-  hipStream_t s = (hipStream_t)stream;
-  const int ncol = c->count;
-  const int dt = dtype_of(mode);
-  std::vector<double> raw_f(ncol, 0.0);
-  std::vector<uint64_t> raw_u(ncol, 0);
-  std::vector<int> Eh(ncol, 0);
-  int ovf_h = 0;
-  if (P.root_kind == ROOT_VERTEX) {
-    // every vertex is one colourful map of a one-vertex template
-    for (int j = 0; j < ncol; ++j) {
-      raw_f[j] = (double)g->n;
-      raw_u[j] = (uint64_t)g->n;
-    }
-    Eh.assign(ncol, 0);
-  } else {
-    const int b = choose_batch(P, ncol, dt, g->n, g->n_slots);
-    Ctx x;
-    ST_TRY(prepare(x, plan, (sg2v_graph *)g, c, mode, b, s, PassOpts()));
-    ST_TRY(prewarm(x, b));
-    ST_TRY(prewarm(x, ncol % b));
-    ST_TRY(x.ws->result.ensure((size_t)ncol * 12 + 64));
-    void *res = x.ws->result.p;
-    int *Ed = (int *)((char *)res + (size_t)ncol * 8);
-    launch_fill_u32((unsigned *)x.ovf, 1, 0u, s);
-    ST_TRY(enqueue_count(x, ncol, b, res, Ed));
-    HIP_TRY(hipMemcpyAsync(dt == DT_U64 ? (void *)raw_u.data() : (void *)raw_f.data(), res,
-                           ncol * 8, hipMemcpyDeviceToHost, s));
-    if (dt == DT_F32) HIP_TRY(hipMemcpyAsync(Eh.data(), Ed, ncol * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&ovf_h, x.ovf, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+  if (plan->p.roots.size() != 1) {
+    set_error("sg2v_count: the plan holds %d templates; use sg2v_count_multi",
+              (int)plan->p.roots.size());
+    return SG2V_EINVAL;
   }
-  finish_counts(P, ncol, P.root_kind == ROOT_VERTEX ? DT_F64 : dt, raw_f.data(), raw_u.data(),
-                Eh.data(), colorful, colorful_u64, estimate, mean_estimate);
-  if (colorful_u64 && P.root_kind == ROOT_VERTEX)
-    for (int j = 0; j < ncol; ++j) colorful_u64[j] = raw_u[j];
+  std::vector<double> rf;
+  std::vector<uint64_t> ru;
+  std::vector<int> E;
+  int ovf_h = 0;
+  ST_TRY(count_raw(plan, g, c, mode, (hipStream_t)stream, rf, ru, E, &ovf_h));
+  finish_template(plan->p, 0, c->count, dtype_of(mode), rf, ru, E, colorful, colorful_u64,
+                  estimate, mean_estimate);
+  if (overflow) *overflow = ovf_h;
+  return SG2V_OK;
+}
+
+extern "C" sg2v_status sg2v_count_multi(const sg2v_plan *plan, const sg2v_graph *g,
+                                        const sg2v_colorings *c, sg2v_mode mode, void *stream,
+                                        double *colorful, uint64_t *colorful_u64,
+                                        double *estimate, double *mean_estimate,
+                                        double *frequency, int32_t *overflow) {
+  ST_TRY(check_inputs(plan, g, c, mode));
+  const Plan &P = plan->p;
+  const int ncol = c->count;
+  const int nr = (int)P.roots.size();
+  std::vector<double> rf;
+  std::vector<uint64_t> ru;
+  std::vector<int> E;
+  int ovf_h = 0;
+  ST_TRY(count_raw(plan, g, c, mode, (hipStream_t)stream, rf, ru, E, &ovf_h));
+  std::vector<double> means(nr, 0.0);
+  for (int r = 0; r < nr; ++r)
+    finish_template(P, r, ncol, dtype_of(mode), rf, ru, E,
+                    colorful ? colorful + (size_t)r * ncol : nullptr,
+                    colorful_u64 ? colorful_u64 + (size_t)r * ncol : nullptr,
+                    estimate ? estimate + (size_t)r * ncol : nullptr, &means[r]);
+  double total = 0.0;
+  for (double m : means) total += m;
+  for (int r = 0; r < nr; ++r) {
+    if (mean_estimate) mean_estimate[r] = means[r];
+    if (frequency) frequency[r] = total > 0.0 ? means[r] / total : 0.0;
+  }
   if (overflow) *overflow = ovf_h;
   return SG2V_OK;
 }
@@ -1743,6 +1844,10 @@ extern "C" sg2v_status sg2v_count_noalloc(const sg2v_plan *plan, const sg2v_grap
                                           double *estimate, double *mean_estimate,
                                           int32_t *overflow) {
   ST_TRY(check_inputs(plan, g, c, mode));
+  if (plan->p.roots.size() != 1) {
+    set_error("sg2v_count_noalloc: the plan holds %d templates", (int)plan->p.roots.size());
+    return SG2V_EINVAL;
+  }
   const Plan &P = plan->p;
   hipStream_t s = (hipStream_t)stream;
   const int ncol = c->count;
@@ -1789,6 +1894,7 @@ extern "C" sg2v_status sg2v_count_noalloc(const sg2v_plan *plan, const sg2v_grap
       }
       x.reset(new Ctx());
       sg2v_status st = prepare(*x, plan, (sg2v_graph *)g, c, mode, b, s, PassOpts(), &ws);
+      x->res_stride = ncol;
       if (st == SG2V_OK) st = prewarm(*x, b);
       if (st == SG2V_OK) st = prewarm(*x, ncol % b);
       if (st == SG2V_OK) st = ws.result.ensure((size_t)ncol * 12 + 64);
@@ -1814,10 +1920,8 @@ extern "C" sg2v_status sg2v_count_noalloc(const sg2v_plan *plan, const sg2v_grap
     HIP_TRY(hipMemcpyAsync(&ovf_h, x->ovf, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
-  finish_counts(P, ncol, P.root_kind == ROOT_VERTEX ? DT_F64 : dt, raw_f.data(), raw_u.data(),
-                Eh.data(), colorful, colorful_u64, estimate, mean_estimate);
-  if (colorful_u64 && P.root_kind == ROOT_VERTEX)
-    for (int j = 0; j < ncol; ++j) colorful_u64[j] = raw_u[j];
+  finish_template(P, 0, ncol, dt, raw_f, raw_u, Eh, colorful, colorful_u64, estimate,
+                  mean_estimate);
   if (overflow) *overflow = ovf_h;
   return SG2V_OK;
 }
@@ -1833,7 +1937,7 @@ extern "C" sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph 
     return SG2V_EINVAL;
   }
   const Node &nd = P.nodes[node];
-  if ((kind == 0 && (nd.size == 1 || node == P.root)) || (kind == 1 && nd.n_passive_uses == 0)) {
+  if ((kind == 0 && (nd.size == 1 || P.root_index[node] >= 0)) || (kind == 1 && nd.n_passive_uses == 0)) {
     set_error("sg2v_debug_table: node %d has no materialised %s table", node, kind ? "B" : "M");
     return SG2V_EINVAL;
   }
@@ -1914,11 +2018,16 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
     set_error("sg2v_count_batch: bad argument");
     return SG2V_EINVAL;
   }
-  for (int p = 0; p < n_plans; ++p)
+  for (int p = 0; p < n_plans; ++p) {
+    if (plans[p] && plans[p]->p.roots.size() != 1) {
+      set_error("sg2v_count_batch: plan %d holds several templates; use sg2v_count_multi", p);
+      return SG2V_EINVAL;
+    }
     if (!plans[p] || plans[p]->p.root_kind == ROOT_VERTEX) {
       set_error("sg2v_count_batch: plan %d is null or a one-vertex template", p);
       return SG2V_EINVAL;
     }
+  }
   if (mode != SG2V_FP64 && mode != SG2V_FP32S && mode != SG2V_U64) {
     set_error("sg2v_count_batch: unknown mode %d", mode);
     return SG2V_EINVAL;
@@ -2088,7 +2197,7 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
     HIP_TRY(hipMemcpyAsync(E.data(), Ed, (size_t)n_plans * ncol * 4, hipMemcpyDeviceToHost, us));
   HIP_TRY(hipStreamSynchronize(us));
   for (int p = 0; p < n_plans; ++p)
-    finish_counts(plans[p]->p, ncol, dt, rf.data() + (size_t)p * ncol, ru.data() + (size_t)p * ncol,
+    finish_counts(plans[p]->p.roots[0], ncol, dt, rf.data() + (size_t)p * ncol, ru.data() + (size_t)p * ncol,
                   E.data() + (size_t)p * ncol, colorful ? colorful + (size_t)p * ncol : nullptr,
                   nullptr, estimate ? estimate + (size_t)p * ncol : nullptr, nullptr);
   return SG2V_OK;
@@ -2370,6 +2479,10 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
                                        const double *grad_colorful, void *grad_w,
                                        void *stream) {
   ST_TRY(check_inputs(plan, g, c, mode));
+  if (plan->p.roots.size() != 1) {
+    set_error("sg2v_count_grad: the plan holds several templates (one template only)");
+    return SG2V_EINVAL;
+  }
   if (mode != SG2V_FP64 && mode != SG2V_FP32S) {
     set_error("sg2v_count_grad: mode must be SG2V_FP64 or SG2V_FP32S");
     return SG2V_EINVAL;
@@ -2630,8 +2743,8 @@ extern "C" void sg2v_plan_destroy(sg2v_plan *plan) {
     (void)hipSetDevice(d.device);
     for (void *q : d.pairs) (void)hipFree(q);
     for (void *q : d.drop) (void)hipFree(q);
-    (void)hipFree(d.root_list);
-    (void)hipFree(d.root_list16);
+    for (void *p : d.root_list) (void)hipFree(p);
+    for (void *p : d.root_list16) (void)hipFree(p);
     for (void *q : d.tr_a) (void)hipFree(q);
     for (void *q : d.tr_p) (void)hipFree(q);
     for (void *q : d.add) (void)hipFree(q);
@@ -2718,8 +2831,8 @@ void tune_file_store(const std::string &key, const sg2v_tuning_t &t) {
 
 extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g, sg2v_mode mode,
                                      int32_t n_colorings, void *stream, sg2v_tuning_t *out) {
-  if (!plan || !g || n_colorings < 1) {
-    set_error("sg2v_autotune: bad argument");
+  if (!plan || !g || n_colorings < 1 || plan->p.roots.size() != 1) {
+    set_error("sg2v_autotune: bad argument (null handle, no colourings or several templates)");
     return SG2V_EINVAL;
   }
   const std::string key = tune_key(plan->p, g, mode, n_colorings);
