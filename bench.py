@@ -75,7 +75,7 @@ def kernel_sha():
     return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 
-def load_traffic(launches_per_colouring):
+def load_traffic(launches_per_colouring, relabel):
     """HBM bytes per SpMM launch from committed rocprofv3 counter runs, if they
     were taken on the current kernel source with the same launches per
     colouring (the launch configuration)."""
@@ -86,6 +86,8 @@ def load_traffic(launches_per_colouring):
     if d.get("kernel_source_sha") != kernel_sha():
         return None
     if d.get("spmm_launches_per_colouring") != launches_per_colouring:
+        return None
+    if int(d.get("graph_relabel", 0)) != relabel:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -103,10 +105,14 @@ def pmc_per_dispatch(db, counter):
     return [(r[1], float(r[2])) for r in rows]
 
 
-def write_traffic(spmm_fetch, spmm_write, copy_fetch, copy_write, copy_mib):
-    """HBM bytes per SpMM launch from rocprofv3 --pmc FETCH_SIZE and
-    WRITE_SIZE runs (KiB per dispatch), each scaled by what the same counter
-    reads for a device copy of copy_mib MiB."""
+def write_traffic(spmm_fetch, spmm_write, copy_fetch, copy_write, gather_fetch, gather_write,
+                  mib, relabel):
+    """HBM-side bytes per SpMM launch from rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch).  Reads are scaled by what FETCH_SIZE
+    reads for a gather of known size (random 256-byte rows of a table of
+    `mib` MiB, each row read once: the SpMM's access pattern), writes by what
+    WRITE_SIZE reads for a linear device copy of `mib` MiB.  FETCH_SIZE counts
+    L2 read misses, Infinity Cache hits included: an upper bound on HBM reads."""
     def mean_of(db, counter, pick):
         v = [x for name, x in pmc_per_dispatch(db, counter) if pick(name)]
         if not v:
@@ -115,23 +121,38 @@ def write_traffic(spmm_fetch, spmm_write, copy_fetch, copy_write, copy_mib):
 
     is_spmm = lambda name: "k_spmm<float" in name  # noqa: E731
     is_copy = lambda name: "copyBuffer" in name  # noqa: E731
-    nbytes = copy_mib * (1 << 20)
+    is_gather = lambda name: "gather" in name.lower()  # noqa: E731
+    nbytes = mib * (1 << 20)
     cf, _ = mean_of(copy_fetch, "FETCH_SIZE", is_copy)
     cw, _ = mean_of(copy_write, "WRITE_SIZE", is_copy)
-    f_fetch, f_write = nbytes / (cf * 1024.0), nbytes / (cw * 1024.0)
+    gf, _ = mean_of(gather_fetch, "FETCH_SIZE", is_gather)
+    gw, _ = mean_of(gather_write, "WRITE_SIZE", is_gather)
+    f_fetch_lin, f_write = nbytes / (cf * 1024.0), nbytes / (cw * 1024.0)
+    # a gather dispatch reads exactly the rows it writes (linearly): its read
+    # bytes are its WRITE_SIZE scaled by the copy's write factor
+    gather_bytes = gw * 1024.0 * f_write
+    f_fetch = gather_bytes / (gf * 1024.0)
     sf, nf = mean_of(spmm_fetch, "FETCH_SIZE", is_spmm)
     sw, nw = mean_of(spmm_write, "WRITE_SIZE", is_spmm)
     rd, wr = sf * 1024.0 * f_fetch, sw * 1024.0 * f_write
     out = {"kernel": "k_spmm<float,...>", "kernel_source_sha": kernel_sha(),
+           "graph_relabel": relabel,
            "spmm_launches_per_colouring": nf,
            "hbm_bytes_per_launch": rd + wr, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+           "read_bytes_per_launch_linear_calibration": sf * 1024.0 * f_fetch_lin,
            "launches": [nf, nw], "fetch_size_kib_per_launch": sf, "write_size_kib_per_launch": sw,
-           "calibration": {"copy_bytes": nbytes, "fetch_factor": f_fetch, "write_factor": f_write},
+           "calibration": {"copy_bytes": nbytes, "gather_bytes_per_dispatch": gather_bytes,
+                           "fetch_factor_gather": f_fetch, "fetch_factor_linear_copy": f_fetch_lin,
+                           "write_factor_linear_copy": f_write},
+           "note": "FETCH_SIZE counts L2 read misses including Infinity Cache hits: the read "
+                   "bytes are an upper bound on HBM reads",
            "runs": ["rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --steps 1 --warmup 0 "
-                    "--no-cpu-baseline --no-fp64 --colorings 1",
+                    f"--no-cpu-baseline --no-fp64 --no-batch-workload --colorings 1 --relabel {relabel}",
                     "rocprofv3 --pmc WRITE_SIZE -- (same)",
-                    f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --calibrate-copy {copy_mib}",
-                    f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --calibrate-copy {copy_mib}"]}
+                    f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --calibrate-copy {mib}",
+                    f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --calibrate-copy {mib}",
+                    f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --calibrate-gather {mib}",
+                    f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --calibrate-gather {mib}"]}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -210,9 +231,11 @@ def batch_workload(sg, gg, torch, reps=3):
         t_given, cf_given = graph_ms([sg.Plan(p) for p in given])
         t_graph, cf = graph_ms(plans)
         cur = sg.get_tuning()
-        sg.set_tuning(cur.spmm_width, cur.ema_rows, cur.batch, cur.budget_bytes, cur.flags | sg.TUNE_BATCH_SERIAL)
+        serial = sg.get_tuning()
+        serial.flags |= sg.TUNE_BATCH_SERIAL
+        sg.restore_tuning(serial)
         t_serial, _ = graph_ms(plans)
-        sg.set_tuning(cur.spmm_width, cur.ema_rows, cur.batch, cur.budget_bytes, cur.flags)
+        sg.restore_tuning(cur)
         for p, par in zip(plans, pars):  # warm
             sg.count(p, g, sg.Colorings(g, len(par), seed, ncol), "fp32s")
         torch.cuda.synchronize()
@@ -351,19 +374,43 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--cpu-scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--relabel", type=int, default=1, choices=(0, 1),
+                    help="register the graph with SG2V_GRAPH_RELABEL (vertices by degree, dealt "
+                         "round-robin to the XCD neighbour ranges); counts are identical")
+    ap.add_argument("--tune-flags", type=int, default=0,
+                    help="extra sg2v tuning flags for the timed FP32 steps (e.g. 1024: row-panel SpMM)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch-workload", action="store_true",
                     help="skip the multi-template batch and adjoint measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
-    ap.add_argument("--traffic-from", nargs=4, metavar=("SPMM_FETCH", "SPMM_WRITE", "COPY_FETCH", "COPY_WRITE"),
-                    help="write the SpMM traffic file from four rocprofv3 --pmc databases "
-                         "(--calibrate-copy gives the copy size, default 1024 MiB) and exit")
+    ap.add_argument("--calibrate-gather", type=int, default=0, metavar="MIB",
+                    help="only gather every 256-byte row of a MIB MiB table once in random "
+                         "order (3 times; calibrates FETCH_SIZE for row gathers) and exit")
+    ap.add_argument("--traffic-from", nargs=6,
+                    metavar=("SPMM_FETCH", "SPMM_WRITE", "COPY_FETCH", "COPY_WRITE", "GATHER_FETCH",
+                             "GATHER_WRITE"),
+                    help="write the SpMM traffic file from six rocprofv3 --pmc databases "
+                         "(--calibrate-copy gives the calibration size, default 1024 MiB) and exit")
     args = ap.parse_args()
 
     if args.traffic_from:
-        write_traffic(*args.traffic_from, args.calibrate_copy or 1024)
+        write_traffic(*args.traffic_from, args.calibrate_copy or 1024, args.relabel)
+        return
+
+    if args.calibrate_gather:
+        import torch
+        rows = args.calibrate_gather * (1 << 20) // 256
+        table = torch.rand(rows, 64, dtype=torch.float32, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        idx = torch.randperm(rows, device="cuda", generator=g)
+        out = torch.empty_like(table)
+        for _ in range(3):
+            torch.index_select(table, 0, idx, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_gather_bytes": rows * 256, "gathers": 3}))
         return
 
     if args.calibrate_copy:
@@ -397,7 +444,9 @@ def main():
     G = gg.rmat(args.scale, args.edges, seed=args.seed)
     log(f"graph: RMAT scale {args.scale}, n={G.n}, nnz={G.nnz}, max deg {int(G.degrees().max())} "
         f"({time.perf_counter() - t0:.1f} s)")
-    g = sg.Graph.from_csr(G)
+    t0 = time.perf_counter()
+    g = sg.Graph.from_csr(G, relabel=bool(args.relabel))
+    log(f"graph registered (relabel={args.relabel}, {time.perf_counter() - t0:.1f} s)")
     plan = sg.Plan(parent, k)
     info = plan.info()
     torch.cuda.synchronize()
@@ -406,7 +455,11 @@ def main():
         c = sg.Colorings(g, k, args.seed, ncol, first=first)
         return sg.count(plan, g, c, mode)
 
-    # batched FP32 with per-column exponents
+    # FP32 with per-column exponents
+    if args.tune_flags:
+        cur = sg.get_tuning()
+        cur.flags |= args.tune_flags
+        sg.restore_tuning(cur)
     for w in range(args.warmup):
         step("fp32s", 1000 + w * ncol)
         log(f"warmup step {w} done")
@@ -428,7 +481,9 @@ def main():
     err = None
     if not args.no_fp64:
         old = sg.get_tuning()
-        sg.set_tuning(old.spmm_width, old.ema_rows, 1, old.budget_bytes, old.flags)
+        one = sg.get_tuning()
+        one.batch = 1
+        sg.restore_tuning(one)
         try:
             torch.cuda.synchronize()
             t2 = time.perf_counter()
@@ -450,7 +505,7 @@ def main():
     achieved = sp["bytes"] / (sp["ms"] * 1e-3) / 1e9 if sp["ms"] > 0 else 0.0
     # measured HBM bytes per SpMM launch (rocprofv3 counters)
     traffic = load_traffic(sp["launches"] // (args.steps * ncol) if sp["launches"] % (args.steps * ncol) == 0
-                           else None)
+                           else None, args.relabel)
     total_bytes = sum(v["bytes"] for v in prof.values())
     kernels = {kk: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps,
                     "model_GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else 0.0}
@@ -473,6 +528,8 @@ def main():
             "graph": {"generator": "rmat", "scale": args.scale, "a_b_c": list(gg.RMAT_ABC),
                       "n": G.n, "nnz": G.nnz, "seed": args.seed},
             "template": "bintree15", "k": k, "colorings_per_step": ncol,
+            "relabel": bool(args.relabel),
+            "tune_flags": args.tune_flags,
             "passes_per_step": passes,
             "colorings_per_pass": ncol / passes if passes else None,
             "mode": ("fp32 mantissa + per-column exponent; one colouring per pass (a single "

@@ -176,6 +176,17 @@ sg2v_status sg2v_plan_pairs(const sg2v_plan *plan, int32_t node, int32_t *out);
 
 #define SG2V_GRAPH_DEVICE_PTRS 1u /* row_ptr/col_idx/w are device pointers, borrowed */
 #define SG2V_GRAPH_VALIDATE 2u    /* check sorted rows, no loops/duplicates, symmetry */
+#define SG2V_GRAPH_RELABEL 4u     /* store the vertices renumbered by decreasing degree (ties in
+                                     the caller's order) and dealt round-robin to the eight
+                                     neighbour ranges of the SpMM's XCD split, so that each range
+                                     holds an equal mix of hubs and low-degree vertices with its
+                                     hubs first and together.  Invisible
+                                     to the caller: a vertex is coloured by its caller id, so
+                                     counts are identical (exact in U64) with and without it;
+                                     sg2v_colorings_download and sg2v_debug_table return rows in
+                                     the caller's vertex order and sg2v_count_grad writes
+                                     gradients in the caller's entry order.  The arrays are
+                                     copied (also with DEVICE_PTRS). */
 
 /* Register an undirected graph as symmetric CSR with n vertices and nnz
  * directed entries (each undirected edge appears as (i,j) and (j,i)).
@@ -244,7 +255,10 @@ sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_co
  * size it needed.
  * Set-up: the plan's split tables must already be on the device (one
  * sg2v_count call with the plan on that device uploads them; SG2V_ENOMEM
- * otherwise).  The graph's task tables are made by sg2v_graph_create.
+ * otherwise).  The graph's task tables are made by sg2v_graph_create (for the
+ * default split threshold; other thresholds, and the row panels of
+ * SG2V_TUNE_SPMM_PANEL, must have been used by an sg2v_count on the graph, or
+ * the call returns SG2V_ENOMEM, respectively runs the default SpMM).
  * Every call on one device shares its area, which keeps the last call's
  * contents: calls that overlap on one device (other threads, other streams)
  * race.  The call synchronises `stream` before it returns. */
@@ -400,6 +414,11 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
                                       instead of parallel graph branches with a workspace each */
 #define SG2V_TUNE_ROOT_THREAD 256 /* narrow root tables read by one thread per vertex from global
                                      memory instead of staged in LDS a tile of rows at a time */
+#define SG2V_TUNE_SPMM_PANEL 1024 /* SpMM over row panels with column-sorted entries (the
+                                     CSC-Split layout of Alg. 6): up to 32 consecutive tasks per
+                                     panel, the panel's entries sorted by neighbour, one wave per
+                                     panel accumulating its rows in LDS; built on first use per
+                                     graph (about 5 bytes per entry, plus 4 with weights) */
 typedef struct {
   int32_t spmm_width;
   int32_t ema_rows;
@@ -410,6 +429,8 @@ typedef struct {
                             (0: as many as 8 GB of range-partial rows hold) */
   int32_t launch_chunks; /* column chunks per SpMM launch without the split
                             (0: 65,535, the grid limit) */
+  int32_t xsplit_min;    /* tasks of at least this many neighbours take the neighbour-range
+                            split (0: 512) */
 } sg2v_tuning_t;
 
 sg2v_status sg2v_set_tuning(const sg2v_tuning_t *t);
@@ -417,7 +438,8 @@ sg2v_status sg2v_get_tuning(sg2v_tuning_t *t);
 
 /* Autotuner: time sg2v_count of `plan` on `g` (n_colorings probe colourings,
  * `mode`) over a small set of candidate settings -- SpMM chunk width, colour
- * skipping, gathers in flight, neighbour-range split, eMA rows per tile,
+ * skipping, gathers in flight, neighbour-range split and its threshold,
+ * row-panel SpMM, eMA rows per tile,
  * colourings per pass; widths that give the same row segments are tried once;
  * each candidate runs once untimed, then the median of three timed runs
  * counts -- and install the fastest

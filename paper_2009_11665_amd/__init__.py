@@ -28,6 +28,7 @@ MODES = {"fp64": FP64, "fp32s": FP32S, "u64": U64}
 
 GRAPH_DEVICE_PTRS = 1
 GRAPH_VALIDATE = 2
+GRAPH_RELABEL = 4
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTTREE", -3: "ERANGE", -4: "ENOMEM", -5: "EGRAPH",
            -6: "EDEVICE"}
@@ -71,7 +72,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("spmm_width", ctypes.c_int32), ("ema_rows", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("budget_bytes", ctypes.c_int64), ("xsplit_group", ctypes.c_int32),
-                ("launch_chunks", ctypes.c_int32)]
+                ("launch_chunks", ctypes.c_int32), ("xsplit_min", ctypes.c_int32)]
 
 
 EXPORTS = ["sg2v_last_error", "sg2v_version", "sg2v_plan_create", "sg2v_plan_destroy",
@@ -261,9 +262,10 @@ class Graph:
     Pass numpy arrays (copied to the device) or torch device tensors
     (borrowed: the Graph keeps references to them)."""
 
-    def __init__(self, n: int, row_ptr, col_idx, w=None, validate: bool = False, stream=None):
+    def __init__(self, n: int, row_ptr, col_idx, w=None, validate: bool = False, stream=None,
+                 relabel: bool = False):
         self.n = int(n)
-        flags = GRAPH_VALIDATE if validate else 0
+        flags = (GRAPH_VALIDATE if validate else 0) | (GRAPH_RELABEL if relabel else 0)
         self._keep = None
         if isinstance(row_ptr, np.ndarray):
             rp = np.ascontiguousarray(row_ptr, np.int64)
@@ -286,10 +288,13 @@ class Graph:
         self.h = h
 
     @classmethod
-    def from_csr(cls, g, validate: bool = False, weighted: Optional[bool] = None, stream=None):
-        """From any object with n, row_ptr, col_idx, w (numpy)."""
+    def from_csr(cls, g, validate: bool = False, weighted: Optional[bool] = None, stream=None,
+                 relabel: bool = False):
+        """From any object with n, row_ptr, col_idx, w (numpy).  relabel: store
+        the vertices renumbered by decreasing degree (SG2V_GRAPH_RELABEL)."""
         use_w = g.w if (weighted is None or weighted) else None
-        return cls(g.n, g.row_ptr, g.col_idx, use_w, validate=validate, stream=stream)
+        return cls(g.n, g.row_ptr, g.col_idx, use_w, validate=validate, stream=stream,
+                   relabel=relabel)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -446,11 +451,13 @@ TUNE_XSPLIT = 32
 TUNE_ROOT_ROWS = 64
 TUNE_ROOT_THREAD = 256
 TUNE_BATCH_SERIAL = 512
+TUNE_SPMM_PANEL = 1024
 
 
 def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,
-               flags: int = 0, xsplit_group: int = 0, launch_chunks: int = 0):
-    t = Tuning(spmm_width, ema_rows, batch, flags, budget_bytes, xsplit_group, launch_chunks)
+               flags: int = 0, xsplit_group: int = 0, launch_chunks: int = 0, xsplit_min: int = 0):
+    t = Tuning(spmm_width, ema_rows, batch, flags, budget_bytes, xsplit_group, launch_chunks,
+               xsplit_min)
     _check(lib().sg2v_set_tuning(ctypes.byref(t)), "sg2v_set_tuning")
 
 

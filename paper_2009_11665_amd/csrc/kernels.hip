@@ -20,24 +20,42 @@ __device__ inline uint64_t fin64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// orig (nullable): caller's vertex id of each stored vertex (graphs renumbered
+// by degree), so a vertex keeps its colour under the renumbering.
 __global__ void k_color(uint8_t *__restrict__ out, int64_t n, int32_t k, uint64_t seed,
-                        int32_t first, int32_t count) {
+                        int32_t first, int32_t count, const int32_t *__restrict__ orig) {
   int64_t total = n * count;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
        x += (int64_t)gridDim.x * blockDim.x) {
     int64_t j = x / n, v = x - j * n;
-    uint64_t h = fin64(seed ^ fin64(((uint64_t)(first + j) << 40) | (uint64_t)v));
+    const uint64_t u = orig ? (uint64_t)orig[v] : (uint64_t)v;
+    uint64_t h = fin64(seed ^ fin64(((uint64_t)(first + j) << 40) | u));
     out[x] = (uint8_t)(((h >> 32) * (uint64_t)k) >> 32);
   }
 }
 
 void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
-                  int32_t count, hipStream_t s) {
+                  int32_t count, const int32_t *orig, hipStream_t s) {
   int64_t total = n * count;
   int64_t blocks = (total + BLOCK - 1) / BLOCK;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  k_color<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(out, n, k, seed, first, count);
+  k_color<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(out, n, k, seed, first, count, orig);
+}
+
+// out[idx[e]] = in[e] (per-entry gradients back to the caller's entry order)
+__global__ void k_scatter_f64(const double *__restrict__ in, const int64_t *__restrict__ idx,
+                              double *__restrict__ out, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[idx[e]] = in[e];
+}
+
+void launch_scatter_f64(const double *in, const int64_t *idx, double *out, int64_t n,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = std::min<int64_t>((n + BLOCK - 1) / BLOCK, 65536);
+  k_scatter_f64<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(in, idx, out, n);
 }
 
 // ===========================================================================
@@ -392,8 +410,10 @@ __global__ void __launch_bounds__(BLOCK) k_xsplit_combine(XsplitCombineArgs a) {
 
 // Split points of every task's neighbour list at the range boundaries
 // r * ceil(n / xs), r = 0..xs (neighbour lists are sorted).
+// bounds (nullable): xs + 1 range starts in vertex ids, else equal ranges of n / xs
 __global__ void k_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
-                             int64_t n_tasks, int64_t n, int xs, uint16_t *out) {
+                             int64_t n_tasks, int64_t n, int xs, const int64_t *bounds,
+                             uint16_t *out) {
   const int64_t span = (n + xs - 1) / xs;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_tasks * (xs + 1);
        q += (int64_t)gridDim.x * blockDim.x) {
@@ -401,7 +421,7 @@ __global__ void k_task_split(const int32_t *col_idx, const int64_t *task_beg, co
     const int r = (int)(q - t * (xs + 1));
     const int32_t *c = col_idx + task_beg[t];
     int lo = 0, hi = task_len[t];
-    const int64_t bound = (int64_t)r * span;
+    const int64_t bound = bounds ? bounds[r] : (int64_t)r * span;
     while (lo < hi) {  // first entry with column >= bound
       const int mid = (lo + hi) >> 1;
       if (c[mid] < bound) lo = mid + 1; else hi = mid;
@@ -464,6 +484,151 @@ __global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
 // columns C and keeps R accumulators.  Pair indices are stored
 // pair-major ([q][C]) so that a wave reads them coalesced.  Blocks walk row
 // tiles with a grid stride; the running column maximum sits in LDS.
+
+// ===========================================================================
+// Row-panel SpMM with column-sorted entries (the CSC-Split layout of Alg. 6,
+// Sec. 5.3): the tasks are grouped in panels of at most PANEL_TASKS
+// consecutive tasks; a panel's entries are sorted by neighbour id, so entries
+// that gather the same neighbour row are adjacent (one cache line request
+// serves the lanes that share it) and the gathered rows are visited in
+// increasing address order.  One wave owns a panel: its rows accumulate in
+// the wave's own LDS rows (LDS atomics, so entries of one instruction that
+// hit the same row are added in the hardware's fixed lane order; no other
+// wave touches them, so results do not depend on scheduling), then go to B
+// or to the long-row partial slots like k_spmm's.  One column chunk of
+// W = G * N columns per blockIdx.y.
+
+template <typename T>
+__device__ inline void lds_add(T *p, T v, bool &ovf) {
+  if constexpr (is_u64<T>) {
+    const T old = atomicAdd((unsigned long long *)p, (unsigned long long)v);
+    ovf |= old + v < old;
+  } else {
+    (void)ovf;
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+}
+
+template <typename T, int G, bool WEIGHTED>
+__global__ void __launch_bounds__(BLOCK) k_spmm_panel(SpmmPanelArgs a) {
+  constexpr int N = V16<T>::N;
+  constexpr int W = G * N;
+  constexpr int E = WAVE / G;  // entries per wave step
+  constexpr int UNR = 4;       // steps in flight
+  using A = Arith<T>;
+  extern __shared__ __align__(16) unsigned char panel_lds[];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const int sub = lane % G;
+  const int q = lane / G;
+  T *acc = (T *)panel_lds + (size_t)wv * PANEL_TASKS * W;  // [PANEL_TASKS][W]
+  const int64_t chunk = a.chunk0 + blockIdx.y;
+  const int64_t col0 = chunk * W + sub * N;
+  const int jb = a.chunk_jb ? a.chunk_jb[chunk] : -1;
+  const uint8_t *colj = jb >= 0 ? a.colors + (int64_t)(a.j0 + jb) * a.n : nullptr;
+  const uint32_t umask = jb >= 0 ? a.chunk_union[chunk] : 0xFFFFFFFFu;
+  const uint32_t imask = jb >= 0 ? a.chunk_inter[chunk] : 0u;
+  const T *__restrict__ M = (const T *)a.M;
+  T *__restrict__ B = (T *)a.B;
+  T *__restrict__ Pt = (T *)a.partial;
+  bool ovf = false;
+  T cmax[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) cmax[u] = T(0);
+  for (int64_t p = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv; p < a.n_panels;
+       p += (int64_t)gridDim.x * WAVES_PER_BLOCK) {
+    const int t0 = a.p_task0[p];
+    const int nt = a.p_ntask[p];
+    for (int x = lane; x < PANEL_TASKS * W; x += WAVE) acc[x] = T(0);
+    // rows whose colour is in the chunk's intersection are never read: zeros
+    uint64_t dead = 0;
+    if (colj) dead = __ballot(lane < nt && ((imask >> colj[a.task_row[t0 + lane]]) & 1u));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int64_t beg = a.p_beg[p], end = a.p_beg[p + 1];
+    for (int64_t e0 = beg; e0 < end; e0 += (int64_t)E * UNR) {
+      V16<T> v[UNR];
+      int loc[UNR];
+      T wq[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int64_t e = e0 + (int64_t)u * E + q;
+        loc[u] = -1;
+        wq[u] = T(1);
+        if (e < end) {
+          const int j = a.e_col[e];
+          const int l = a.e_loc[e];
+          if (!((dead >> l) & 1ull) && (!colj || ((umask >> colj[j]) & 1u))) {
+            loc[u] = l;
+            v[u] = *(const V16<T> *)(M + (int64_t)j * a.ldm + col0);
+            if constexpr (WEIGHTED) wq[u] = (T)a.e_w[e];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (loc[u] >= 0) {
+#pragma unroll
+          for (int x = 0; x < N; ++x) {
+            T val = v[u].x[x];
+            if constexpr (WEIGHTED) val = wq[u] * val;
+            lds_add(acc + loc[u] * W + sub * N + x, val, ovf);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int r = q; r < nt; r += E) {
+      V16<T> out = *(const V16<T> *)(acc + r * W + sub * N);
+      const int64_t t = (int64_t)t0 + r;
+      const int row = a.task_row[t];
+      const int slot = a.task_slot[t];
+      if (slot < 0) {
+        if (a.accumulate) {
+          const V16<T> old = *(const V16<T> *)(B + (int64_t)row * a.ldb + col0);
+#pragma unroll
+          for (int u = 0; u < N; ++u) out.x[u] = A::add(out.x[u], old.x[u], ovf);
+        }
+        *(V16<T> *)(B + (int64_t)row * a.ldb + col0) = out;
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+          if (col0 + u < a.ncols_valid && out.x[u] > cmax[u]) cmax[u] = out.x[u];
+      } else {
+        *(V16<T> *)(Pt + (int64_t)slot * a.ldb + col0) = out;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  if constexpr (is_u64<T>) {
+    if (ovf) atomicOr(a.ovf, 1);
+  }
+  if (a.mx) {
+    // each wave's first G floats of its own LDS rows carry its column maxima
+    auto red = [&](int w2, int l) -> float & {
+      return ((float *)(panel_lds + (size_t)w2 * PANEL_TASKS * W * sizeof(T)))[l];
+    };
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      float x = (float)cmax[u];
+      for (int off = G; off < WAVE; off <<= 1) x = fmaxf(x, shfl_xor(x, off));
+      cmax[u] = (T)x;
+    }
+    for (int u = 0; u < N; ++u) {
+      __syncthreads();
+      if (lane < G) red(wv, lane) = (float)cmax[u];
+      __syncthreads();
+      if (wv == 0 && lane < G) {
+        float x = red(0, lane);
+        for (int w2 = 1; w2 < WAVES_PER_BLOCK; ++w2) x = fmaxf(x, red(w2, lane));
+        const int64_t c = chunk * W + lane * N + u;
+        if (c < a.ncols_valid && x > 0.f) atomicMax(a.mx + c, __float_as_uint(x));
+      }
+      __syncthreads();
+    }
+  }
+}
 
 template <typename T, int R, bool SCALED, bool STAGE>
 __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
@@ -1570,6 +1735,31 @@ int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipS
   return spmm_t<uint64_t, 4>(a, G, grid, s);
 }
 
+template <typename T, int G>
+static void panel_g(const SpmmPanelArgs &a, dim3 grid, hipStream_t s) {
+  const size_t lds = (size_t)WAVES_PER_BLOCK * PANEL_TASKS * G * 16;
+  if (a.e_w) k_spmm_panel<T, G, true><<<grid, BLOCK, lds, s>>>(a);
+  else k_spmm_panel<T, G, false><<<grid, BLOCK, lds, s>>>(a);
+}
+
+template <typename T>
+static int panel_t(const SpmmPanelArgs &a, int G, dim3 grid, hipStream_t s) {
+  switch (G) {
+    case 2: panel_g<T, 2>(a, grid, s); return 0;
+    case 4: panel_g<T, 4>(a, grid, s); return 0;
+    case 8: panel_g<T, 8>(a, grid, s); return 0;
+    case 16: panel_g<T, 16>(a, grid, s); return 0;
+    case 32: panel_g<T, 32>(a, grid, s); return 0;
+    default: return -1;
+  }
+}
+
+int launch_spmm_panel(int dtype, const SpmmPanelArgs &a, int G, dim3 grid, hipStream_t s) {
+  if (dtype == DT_F32) return panel_t<float>(a, G, grid, s);
+  if (dtype == DT_F64) return panel_t<double>(a, G, grid, s);
+  return panel_t<uint64_t>(a, G, grid, s);
+}
+
 void launch_xsplit_combine(int dtype, const XsplitCombineArgs &a, hipStream_t s) {
   const int N = (dtype == DT_F32) ? 4 : 2;
   const int64_t nvec = (a.ldp + N - 1) / N;
@@ -1580,11 +1770,12 @@ void launch_xsplit_combine(int dtype, const XsplitCombineArgs &a, hipStream_t s)
 }
 
 void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
-                       int64_t n_tasks, int64_t n, int xs, uint16_t *out, hipStream_t s) {
+                       int64_t n_tasks, int64_t n, int xs, const int64_t *bounds, uint16_t *out,
+                       hipStream_t s) {
   const int64_t total = n_tasks * (xs + 1);
   if (total == 0) return;
   k_task_split<<<grid_cap((total + BLOCK - 1) / BLOCK, 65536), BLOCK, 0, s>>>(col_idx, task_beg, task_len,
-                                                                            n_tasks, n, xs, out);
+                                                                            n_tasks, n, xs, bounds, out);
 }
 
 void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s) {

@@ -73,6 +73,36 @@ struct SpmmArgs {
   void *partial8;
 };
 
+// Row-panel SpMM (column-sorted entries per panel of tasks)
+constexpr int PANEL_TASKS = 32;  // tasks per panel (one wave's LDS rows)
+struct SpmmPanelArgs {
+  const int32_t *p_task0;  // first task of each panel
+  const int32_t *p_ntask;  // tasks in each panel (<= PANEL_TASKS)
+  const int64_t *p_beg;    // [n_panels + 1] entry offsets
+  int64_t n_panels;
+  const int32_t *e_col;    // neighbour of each panel entry
+  const uint8_t *e_loc;    // its task within the panel
+  const float *e_w;        // its weight (nullable: 0/1 adjacency)
+  const int32_t *task_row;
+  const int32_t *task_slot;
+  const void *M;
+  int64_t ldm;
+  void *B;
+  int64_t ldb;
+  void *partial;
+  int64_t ncols_valid;
+  unsigned *mx;
+  int *ovf;
+  int32_t accumulate;
+  const int32_t *chunk_jb;
+  const uint32_t *chunk_union;
+  const uint32_t *chunk_inter;
+  const uint8_t *colors;
+  int32_t j0;
+  int64_t n;
+  int64_t chunk0;
+};
+
 struct XsplitCombineArgs {
   const void *partial8;  // [xsplit][n_tasks][ldp]
   int32_t xsplit;        // 1..8
@@ -199,7 +229,9 @@ struct RootArgs {
 };
 
 void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
-                  int32_t count, hipStream_t s);
+                  int32_t count, const int32_t *orig, hipStream_t s);
+void launch_scatter_f64(const double *in, const int64_t *idx, double *out, int64_t n,
+                        hipStream_t s);
 void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s);
 // unroll: gathers in flight per stream (4 or 8)
 int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipStream_t s);
@@ -208,8 +240,10 @@ void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s);
 // must start at zero
 void launch_colmax(const float *X, int64_t n, int64_t ld, int64_t cols, unsigned *mx, hipStream_t s);
 void launch_xsplit_combine(int dtype, const XsplitCombineArgs &a, hipStream_t s);
+int launch_spmm_panel(int dtype, const SpmmPanelArgs &a, int G, dim3 grid, hipStream_t s);
 void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
-                       int64_t n_tasks, int64_t n, int xs, uint16_t *out, hipStream_t s);
+                       int64_t n_tasks, int64_t n, int xs, const int64_t *bounds, uint16_t *out,
+                       hipStream_t s);
 int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
                        hipStream_t s);
 // grid.y must be 1 (the kernel covers a.nb colourings); lds = nb * Cs * 4

@@ -18,6 +18,7 @@
 #include <memory>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -45,7 +46,7 @@ namespace {
 // ---------------------------------------------------------------------------
 // tuning
 
-sg2v_tuning_t g_tune = {0, 0, 0, 0, 0, 0, 0};
+sg2v_tuning_t g_tune = {0, 0, 0, 0, 0, 0, 0, 0};
 std::mutex g_tune_mu;
 
 sg2v_tuning_t tuning() {
@@ -239,11 +240,29 @@ struct sg2v_graph {
   int64_t *task_beg = nullptr;
   int64_t n_tasks = 0, n_slots = 0;
   std::vector<int32_t> h_task_len;  // sorted lengths
+  std::vector<int64_t> h_task_beg;  // their first entries
+  // row panels with column-sorted entries (SG2V_TUNE_SPMM_PANEL), built on first use
+  struct Panels {
+    int32_t *task0 = nullptr, *ntask = nullptr;
+    int64_t *beg = nullptr;
+    int32_t *col = nullptr;
+    uint8_t *loc = nullptr;
+    float *w = nullptr;
+    int64_t n = 0;
+  };
+  std::unique_ptr<Panels> panels;
   double long_share = 0.0;          // share of the entries in tasks of >= kXsplitMin neighbours
   int32_t *long_row = nullptr, *long_slot0 = nullptr, *long_nslot = nullptr;
   int32_t n_long = 0;
   std::map<int, UnitTable> units;  // by G (lanes per neighbour row segment)
   uint16_t *tsplit = nullptr;      // [n_tasks][kXsplit + 1] neighbour-range split offsets
+  int64_t *xbounds = nullptr;      // device, kXsplit + 1 range starts (renumbered graphs), or null
+  // SG2V_GRAPH_RELABEL: vertices renumbered by decreasing degree
+  bool relabelled = false;
+  int32_t *orig_id = nullptr;      // device, n: caller's id of each stored vertex
+  int64_t *entry_orig = nullptr;   // device, nnz: caller's CSR entry of each stored entry
+  std::shared_ptr<const std::vector<int32_t>> new_of;  // host, n: stored id of each caller id
+  DevBuf grad_tmp;                 // per-entry gradient in stored order (renumbered graphs)
   std::vector<void *> allocs;
   ~sg2v_graph() {
     if (tsplit) (void)hipFree(tsplit);
@@ -257,6 +276,7 @@ struct sg2v_graph {
 };
 
 struct sg2v_colorings {
+  std::shared_ptr<const std::vector<int32_t>> new_of;  // renumbered graph: stored id of a caller id
   int device = 0;
   int64_t n = 0;
   int32_t k = 0, count = 0, first = 0;
@@ -279,7 +299,11 @@ int rpw_for(int64_t len, int G) {
 }
 
 sg2v_status build_units(sg2v_graph *g, int G, hipStream_t s, UnitTable **out) {
-  auto it = g->units.find(G);
+  // units end at the split threshold (tuning's xsplit_min, 512 neighbours by default)
+  const sg2v_tuning_t tu = tuning();
+  const int64_t xmin = tu.xsplit_min > 0 ? std::min<int64_t>(tu.xsplit_min, kSegment) : kXsplitMin;
+  const int key = G + 64 * (int)xmin;
+  auto it = g->units.find(key);
   if (it != g->units.end()) {
     *out = &it->second;
     return SG2V_OK;
@@ -301,14 +325,94 @@ sg2v_status build_units(sg2v_graph *g, int G, hipStream_t s, UnitTable **out) {
   }
   UnitTable U;
   U.n_units = (int64_t)ut.size();
-  while (U.x_units < U.n_units && g->h_task_len[ut[U.x_units]] >= kXsplitMin) ++U.x_units;
+  while (U.x_units < U.n_units && g->h_task_len[ut[U.x_units]] >= xmin) ++U.x_units;
   U.x_tasks = U.x_units < U.n_units ? ut[U.x_units] : g->n_tasks;
   ST_TRY(upload(ut, (void **)&U.unit_task, s));
   ST_TRY(upload(ur, (void **)&U.unit_rpw, s));
   ST_TRY(upload(un, (void **)&U.unit_ntask, s));
   HIP_TRY(hipStreamSynchronize(s));
-  g->units[G] = U;
-  *out = &g->units[G];
+  g->units[key] = U;
+  *out = &g->units[key];
+  return SG2V_OK;
+}
+
+// Row panels for the CSC-Split-style SpMM: consecutive tasks (in their
+// longest-first order) grouped while a panel holds at most PANEL_TASKS tasks
+// and kPanelEntries entries (a longer task gets a panel of its own); each
+// panel's entries sorted by neighbour id, ties by task.
+constexpr int64_t kPanelEntries = 8192;
+
+sg2v_status build_panels(sg2v_graph *g, hipStream_t s, sg2v_graph::Panels **out) {
+  if (g->panels) {
+    *out = g->panels.get();
+    return SG2V_OK;
+  }
+  if (t_noalloc) {
+    set_error("row panels not built for this graph");
+    return SG2V_ENOMEM;
+  }
+  const int64_t nnz = g->nnz;
+  std::vector<int32_t> ci(std::max<int64_t>(nnz, 1));
+  std::vector<float> wv(g->w ? nnz : 0);
+  if (nnz) HIP_TRY(hipMemcpyAsync(ci.data(), g->col_idx, nnz * 4, hipMemcpyDeviceToHost, s));
+  if (g->w && nnz) HIP_TRY(hipMemcpyAsync(wv.data(), g->w, nnz * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int32_t> task0, ntask;
+  std::vector<int64_t> pbeg{0};
+  for (int64_t t = 0; t < g->n_tasks;) {
+    int64_t cnt = 0, ent = 0;
+    task0.push_back((int32_t)t);
+    while (t < g->n_tasks && cnt < PANEL_TASKS && (cnt == 0 || ent + g->h_task_len[t] <= kPanelEntries)) {
+      ent += g->h_task_len[t];
+      ++cnt;
+      ++t;
+    }
+    ntask.push_back((int32_t)cnt);
+    pbeg.push_back(pbeg.back() + ent);
+  }
+  const int64_t np = (int64_t)task0.size();
+  std::vector<int32_t> ecol(std::max<int64_t>(nnz, 1));
+  std::vector<uint8_t> eloc(std::max<int64_t>(nnz, 1));
+  std::vector<float> ew(g->w ? std::max<int64_t>(nnz, 1) : 0);
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int th = 0; th < nth; ++th)
+    pool.emplace_back([&, th]() {
+      std::vector<std::pair<int32_t, int64_t>> ent;  // (neighbour, local task << 40 | entry)
+      for (int64_t p = th; p < np; p += nth) {
+        ent.clear();
+        for (int l = 0; l < ntask[p]; ++l) {
+          const int64_t t = task0[p] + l;
+          const int64_t b = g->h_task_beg[t];
+          for (int64_t e = b; e < b + g->h_task_len[t]; ++e)
+            ent.push_back({ci[e], ((int64_t)l << 40) | e});
+        }
+        std::sort(ent.begin(), ent.end());
+        for (size_t x = 0; x < ent.size(); ++x) {
+          const int64_t o = pbeg[p] + (int64_t)x;
+          ecol[o] = ent[x].first;
+          eloc[o] = (uint8_t)(ent[x].second >> 40);
+          if (g->w) ew[o] = wv[ent[x].second & ((1ll << 40) - 1)];
+        }
+      }
+    });
+  for (auto &t : pool) t.join();
+  std::unique_ptr<sg2v_graph::Panels> P(new sg2v_graph::Panels());
+  void *p;
+  ST_TRY(upload(task0, &p, s)); P->task0 = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(ntask, &p, s)); P->ntask = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(pbeg, &p, s)); P->beg = (int64_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(ecol, &p, s)); P->col = (int32_t *)p; g->allocs.push_back(p);
+  ST_TRY(upload(eloc, &p, s)); P->loc = (uint8_t *)p; g->allocs.push_back(p);
+  if (g->w) {
+    ST_TRY(upload(ew, &p, s));
+    P->w = (float *)p;
+    g->allocs.push_back(p);
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  P->n = np;
+  g->panels = std::move(P);
+  *out = g->panels.get();
   return SG2V_OK;
 }
 
@@ -356,6 +460,7 @@ sg2v_status graph_tasks(sg2v_graph *g, const std::vector<int64_t> &rp, hipStream
   g->n_tasks = T;
   g->n_slots = slots;
   g->h_task_len = slen;
+  g->h_task_beg = sbeg;
   {
     int64_t in_long = 0, all = 0;
     for (int64_t x = 0; x < T; ++x) {
@@ -382,7 +487,7 @@ sg2v_status graph_tasks(sg2v_graph *g, const std::vector<int64_t> &rp, hipStream
 extern "C" sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *row_ptr,
                                          const int32_t *col_idx, const float *w, uint32_t flags,
                                          void *stream, sg2v_graph **out) {
-  if (!out || !row_ptr || (nnz > 0 && !col_idx) || (flags & ~3u)) {
+  if (!out || !row_ptr || (nnz > 0 && !col_idx) || (flags & ~7u)) {
     set_error("sg2v_graph_create: null argument or unknown flag");
     return SG2V_EINVAL;
   }
@@ -396,9 +501,10 @@ extern "C" sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *
   std::vector<int64_t> rp(n + 1);
   std::vector<int32_t> ci;
   std::vector<float> wv;
+  const bool relabel = flags & SG2V_GRAPH_RELABEL;
   if (dev) {
     HIP_TRY(hipMemcpyAsync(rp.data(), row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    if (flags & SG2V_GRAPH_VALIDATE) {
+    if ((flags & SG2V_GRAPH_VALIDATE) || relabel) {
       ci.resize(nnz);
       if (nnz) HIP_TRY(hipMemcpyAsync(ci.data(), col_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
@@ -455,7 +561,71 @@ extern "C" sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *
     mw = std::max(mw, sw);
   }
   g->max_wdeg = mw;
-  if (dev) {
+  if (relabel) {
+    // Vertices by decreasing degree (ties in caller order), dealt round-robin
+    // to the eight neighbour ranges of the XCD split: the vertex of degree
+    // rank q goes to range q mod 8, at position q / 8 within it.  Each range
+    // then holds an equal mix of hubs and low-degree vertices (equal work per
+    // XCD), with its hubs first and together.  Rows are re-sorted.
+    std::vector<int32_t> byd(n);
+    std::iota(byd.begin(), byd.end(), 0);
+    std::stable_sort(byd.begin(), byd.end(), [&](int32_t a, int32_t b) {
+      return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+    });
+    std::vector<int64_t> xb(kXsplit + 1, 0);
+    for (int r = 0; r < kXsplit; ++r) xb[r + 1] = xb[r] + n / kXsplit + (r < n % kXsplit ? 1 : 0);
+    std::vector<int32_t> orig(n);
+    for (int64_t q = 0; q < n; ++q) orig[xb[q % kXsplit] + q / kXsplit] = byd[q];
+    auto nw = std::make_shared<std::vector<int32_t>>(n);
+    for (int64_t v = 0; v < n; ++v) (*nw)[orig[v]] = (int32_t)v;
+    std::vector<int64_t> rp2(n + 1, 0);
+    for (int64_t v = 0; v < n; ++v) rp2[v + 1] = rp2[v] + (rp[orig[v] + 1] - rp[orig[v]]);
+    std::vector<int32_t> ci2(nnz);
+    std::vector<float> w2(hw ? nnz : 0);
+    std::vector<int64_t> eo(nnz);
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int th = 0; th < nth; ++th)
+      pool.emplace_back([&, th]() {
+        std::vector<std::pair<int32_t, int64_t>> row;
+        for (int64_t v = th; v < n; v += nth) {
+          const int64_t u = orig[v];
+          row.clear();
+          for (int64_t e = rp[u]; e < rp[u + 1]; ++e) row.push_back({(*nw)[hc[e]], e});
+          std::sort(row.begin(), row.end());
+          for (size_t q = 0; q < row.size(); ++q) {
+            const int64_t e2 = rp2[v] + (int64_t)q;
+            ci2[e2] = row[q].first;
+            eo[e2] = row[q].second;
+            if (hw) w2[e2] = hw[row[q].second];
+          }
+        }
+      });
+    for (auto &t : pool) t.join();
+    g->relabelled = true;
+    g->new_of = nw;
+    g->owns = true;
+    void *p;
+    ST_TRY(upload(orig, &p, s)); g->orig_id = (int32_t *)p; g->allocs.push_back(p);
+    if (nnz) { ST_TRY(upload(eo, &p, s)); g->entry_orig = (int64_t *)p; g->allocs.push_back(p); }
+    ST_TRY(upload(xb, &p, s)); g->xbounds = (int64_t *)p; g->allocs.push_back(p);
+    HIP_TRY(hipMalloc(&p, (n + 1) * sizeof(int64_t)));
+    g->allocs.push_back(p);
+    g->row_ptr = (int64_t *)p;
+    HIP_TRY(hipMemcpyAsync(p, rp2.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMalloc(&p, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+    g->allocs.push_back(p);
+    g->col_idx = (int32_t *)p;
+    if (nnz) HIP_TRY(hipMemcpyAsync(p, ci2.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (hw) {
+      HIP_TRY(hipMalloc(&p, std::max<int64_t>(nnz, 1) * sizeof(float)));
+      g->allocs.push_back(p);
+      g->w = (float *)p;
+      if (nnz) HIP_TRY(hipMemcpyAsync(p, w2.data(), nnz * sizeof(float), hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));  // host arrays of this scope are read by the copies
+    rp.swap(rp2);
+  } else if (dev) {
     g->owns = false;
     g->row_ptr = (int64_t *)row_ptr;
     g->col_idx = (int32_t *)col_idx;
@@ -510,11 +680,12 @@ extern "C" sg2v_status sg2v_color(const sg2v_graph *g, int32_t k, uint64_t seed,
   c->count = n_colorings;
   c->first = first;
   c->seed = seed;
+  c->new_of = g->new_of;
   HIP_TRY(hipMalloc((void **)&c->d, g->n * n_colorings));
   {
     ProfScope ps(SG2V_K_COLOR, (double)g->n * n_colorings, (double)g->n * n_colorings,
                  (hipStream_t)stream);
-    launch_color(c->d, g->n, k, seed, first, n_colorings, (hipStream_t)stream);
+    launch_color(c->d, g->n, k, seed, first, n_colorings, g->orig_id, (hipStream_t)stream);
   }
   HIP_TRY(hipGetLastError());
   *out = c.release();
@@ -531,6 +702,16 @@ extern "C" sg2v_status sg2v_colorings_download(const sg2v_colorings *c, uint8_t 
   }
   HIP_TRY(hipMemcpyAsync(out, c->d, c->n * c->count, hipMemcpyDeviceToHost, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  if (c->new_of) {
+    // stored order -> the caller's vertex order
+    const std::vector<int32_t> &nw = *c->new_of;
+    std::vector<uint8_t> row(c->n);
+    for (int32_t j = 0; j < c->count; ++j) {
+      uint8_t *o = out + (size_t)j * c->n;
+      std::memcpy(row.data(), o, c->n);
+      for (int64_t v = 0; v < c->n; ++v) o[v] = row[nw[v]];
+    }
+  }
   return SG2V_OK;
 }
 
@@ -1027,7 +1208,8 @@ sg2v_status xsplit_setup(Ctx &x, const UnitTable *U, int64_t nc, int W, int64_t 
   if (!g->tsplit && t_noalloc) return SG2V_OK;  // offsets never built: no split (same counts)
   if (!g->tsplit) {
     HIP_TRY(hipMalloc((void **)&g->tsplit, (size_t)g->n_tasks * (kXsplit + 1) * sizeof(uint16_t)));
-    launch_task_split(g->col_idx, g->task_beg, g->task_len, g->n_tasks, g->n, kXsplit, g->tsplit, x.s);
+    launch_task_split(g->col_idx, g->task_beg, g->task_len, g->n_tasks, g->n, kXsplit, g->xbounds,
+                      g->tsplit, x.s);
     HIP_TRY(hipGetLastError());
   }
   const int64_t chunks = (nc + W - 1) / W;
@@ -1102,10 +1284,56 @@ sg2v_status step_spmm(Ctx &x, int node) {
   a.ldp = 0;
   a.partial8 = nullptr;
   int64_t gch = 0;
-  ST_TRY(xsplit_setup(x, U, nc, W, &gch));
   const double n = (double)x.g->n, nnz = (double)x.g->nnz;
   const double bytes = 2.0 * n * (double)nc * x.es +
                        (double)chunks * (nnz * (4.0 + (x.g->w ? 4.0 : 0.0)) + 20.0 * x.g->n_tasks);
+  sg2v_graph::Panels *PN = nullptr;
+  if (fl & SG2V_TUNE_SPMM_PANEL) {
+    // a noalloc call on a graph whose panels were never built runs k_spmm instead
+    const sg2v_status ps = build_panels(x.g, x.s, &PN);
+    if (ps != SG2V_OK && !t_noalloc) return ps;
+  }
+  if (PN) {
+    SpmmPanelArgs pa{};
+    pa.p_task0 = PN->task0;
+    pa.p_ntask = PN->ntask;
+    pa.p_beg = PN->beg;
+    pa.n_panels = PN->n;
+    pa.e_col = PN->col;
+    pa.e_loc = PN->loc;
+    pa.e_w = PN->w;
+    pa.task_row = x.g->task_row;
+    pa.task_slot = x.g->task_slot;
+    pa.M = a.M;
+    pa.ldm = a.ldm;
+    pa.B = a.B;
+    pa.ldb = a.ldb;
+    pa.partial = a.partial;
+    pa.ncols_valid = nc;
+    pa.mx = a.mx;
+    pa.ovf = a.ovf;
+    pa.accumulate = 0;
+    pa.chunk_jb = a.chunk_jb;
+    pa.chunk_union = a.chunk_union;
+    pa.chunk_inter = a.chunk_inter;
+    pa.colors = a.colors;
+    pa.j0 = a.j0;
+    pa.n = a.n;
+    const int64_t per_launch = fl_launch_chunks();
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>((PN->n + 3) / 4,  // four waves per block
+                                                              kPersistBlocks));
+    for (int64_t c0 = 0; c0 < chunks; c0 += per_launch) {
+      const int64_t gc = std::min<int64_t>(per_launch, chunks - c0);
+      const double frac = (double)gc / (double)chunks;
+      pa.chunk0 = c0;
+      ProfScope ps(SG2V_K_SPMM, bytes * frac, nnz * (double)nc * frac, x.s);
+      if (launch_spmm_panel(x.dt, pa, x.pp.G, dim3((unsigned)gx, (unsigned)gc), x.s)) {
+        set_error("sg2v_count: no panel SpMM variant for G=%d", x.pp.G);
+        return SG2V_EINVAL;
+      }
+    }
+  } else {
+  ST_TRY(xsplit_setup(x, U, nc, W, &gch));
   if (gch == 0) {
     // all chunks in one launch (grid.y is at most 65535: groups beyond that)
     const int64_t per_launch = fl_launch_chunks();
@@ -1166,6 +1394,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
     }
     a.mx = mx;
   }
+  }  // row panels or k_spmm
   CombineArgs cb{};
   cb.partial = a.partial;
   cb.B = B.p;
@@ -1482,9 +1711,10 @@ sg2v_status copy_capture(Ctx &x, const Capture &cap) {
     HIP_TRY(hipMemcpyAsync(e.data(), t.e, nc * 4, hipMemcpyDeviceToHost, x.s));
   }
   HIP_TRY(hipStreamSynchronize(x.s));
-  for (int64_t i = 0; i < n; ++i)
+  const std::vector<int32_t> *nw = x.g->new_of.get();
+  for (int64_t i = 0; i < n; ++i)  // row i of the caller's vertex order
     for (int64_t c = 0; c < nc; ++c) {
-      const size_t src = (size_t)(i * t.ld + c);
+      const size_t src = (size_t)((nw ? (int64_t)(*nw)[i] : i) * t.ld + c);
       if (x.dt == DT_U64) {
         ((uint64_t *)cap.host)[i * nc + c] = ((uint64_t *)raw.data())[src];
       } else if (x.dt == DT_F64) {
@@ -1989,7 +2219,8 @@ std::vector<std::unique_ptr<BatchGraph>> g_batch_cache;
 bool same_tuning(const sg2v_tuning_t &a, const sg2v_tuning_t &b) {
   return a.spmm_width == b.spmm_width && a.ema_rows == b.ema_rows && a.batch == b.batch &&
          a.flags == b.flags && a.budget_bytes == b.budget_bytes &&
-         a.xsplit_group == b.xsplit_group && a.launch_chunks == b.launch_chunks;
+         a.xsplit_group == b.xsplit_group && a.launch_chunks == b.launch_chunks &&
+         a.xsplit_min == b.xsplit_min;
 }
 
 void ws_gens(Workspace &ws, uint64_t *out) {
@@ -2154,7 +2385,7 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
       for (int p = 0; p < n_plans && st == SG2V_OK && he == hipSuccess; ++p) {
         if (conc) he = hipStreamWaitEvent(sp[p], fork, 0);
         if (he != hipSuccess) break;
-        launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, sp[p]);
+        launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, g->orig_id, sp[p]);
         xs[p].s = sp[p];
         xs[p].c = bg->cols[p].get();
         st = enqueue_count(xs[p], ncol, bs[p], res + (size_t)p * ncol * 8, Ed + (size_t)p * ncol);
@@ -2474,10 +2705,33 @@ sg2v_status count_grad_fp32s(const sg2v_plan *plan, sg2v_graph *gg, const sg2v_c
   return SG2V_OK;
 }
 
+namespace {
+sg2v_status count_grad_stored(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
+                              sg2v_mode mode, const double *grad_colorful, void *grad_w,
+                              void *stream);
+}  // namespace
+
 extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *g,
                                        const sg2v_colorings *c, sg2v_mode mode,
                                        const double *grad_colorful, void *grad_w,
                                        void *stream) {
+  if (!g || !g->relabelled || !grad_w)
+    return count_grad_stored(plan, g, c, mode, grad_colorful, grad_w, stream);
+  // renumbered graph: gradients in stored entry order, then back to the caller's
+  sg2v_graph *gg = (sg2v_graph *)g;
+  ST_TRY(gg->grad_tmp.ensure((size_t)std::max<int64_t>(g->nnz, 1) * 8));
+  ST_TRY(count_grad_stored(plan, g, c, mode, grad_colorful, gg->grad_tmp.p, stream));
+  launch_scatter_f64((const double *)gg->grad_tmp.p, g->entry_orig, (double *)grad_w, g->nnz,
+                     (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return SG2V_OK;
+}
+
+namespace {
+sg2v_status count_grad_stored(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
+                              sg2v_mode mode, const double *grad_colorful, void *grad_w,
+                              void *stream) {
   ST_TRY(check_inputs(plan, g, c, mode));
   if (plan->p.roots.size() != 1) {
     set_error("sg2v_count_grad: the plan holds several templates (one template only)");
@@ -2694,6 +2948,7 @@ extern "C" sg2v_status sg2v_count_grad(const sg2v_plan *plan, const sg2v_graph *
   HIP_TRY(hipStreamSynchronize(s));
   return SG2V_OK;
 }
+}  // namespace
 
 extern "C" sg2v_status sg2v_set_tuning(const sg2v_tuning_t *t) {
   if (!t) {
@@ -2815,7 +3070,7 @@ void tune_file_load() {
   std::string key;
   sg2v_tuning_t t{};
   while (in >> key >> t.spmm_width >> t.ema_rows >> t.batch >> t.flags >> t.budget_bytes >>
-         t.xsplit_group >> t.launch_chunks)
+         t.xsplit_group >> t.launch_chunks >> t.xsplit_min)
     g_autotune[key] = t;
 }
 
@@ -2824,7 +3079,8 @@ void tune_file_store(const std::string &key, const sg2v_tuning_t &t) {
   if (!f) return;
   std::ofstream out(f, std::ios::app);
   out << key << " " << t.spmm_width << " " << t.ema_rows << " " << t.batch << " " << t.flags
-      << " " << t.budget_bytes << " " << t.xsplit_group << " " << t.launch_chunks << "\n";
+      << " " << t.budget_bytes << " " << t.xsplit_group << " " << t.launch_chunks << " "
+      << t.xsplit_min << "\n";
 }
 
 }  // namespace
@@ -2857,14 +3113,20 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
   std::vector<sg2v_tuning_t> cand;
   const int widths[] = {16, 32, 64, 128};
   const int rows[] = {4, 8, 16};
-  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_SPMM_UNROLL8 | SG2V_TUNE_XSPLIT;
+  const int skipfl = SG2V_TUNE_NO_COLOR_SKIP | SG2V_TUNE_SPMM_UNROLL4 | SG2V_TUNE_SPMM_UNROLL8 |
+                     SG2V_TUNE_XSPLIT | SG2V_TUNE_SPMM_PANEL;
   for (int w : widths)
     for (int fl : {0, (int)SG2V_TUNE_NO_COLOR_SKIP, (int)SG2V_TUNE_SPMM_UNROLL4, (int)SG2V_TUNE_SPMM_UNROLL8,
-                   (int)SG2V_TUNE_XSPLIT}) {
+                   (int)SG2V_TUNE_XSPLIT, (int)SG2V_TUNE_SPMM_PANEL}) {
       sg2v_tuning_t t = base;
       t.spmm_width = w;
       t.flags = (base.flags & ~skipfl) | fl;
       cand.push_back(t);
+      if (fl == SG2V_TUNE_XSPLIT)  // the split threshold as well
+        for (int xm : {256, 1024}) {
+          t.xsplit_min = xm;
+          cand.push_back(t);
+        }
     }
   // candidates whose chunk width maps to the same row-segment lanes run the
   // same kernels: keep the first of each
@@ -2877,7 +3139,7 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
     std::vector<sg2v_tuning_t> uniq;
     for (auto &t : cand) {
       ST_TRY(sg2v_set_tuning(&t));
-      const std::pair<int, int> key(pick_G(dt, widest, g->n), t.flags);
+      const std::pair<int, int> key(pick_G(dt, widest, g->n), t.flags + (t.xsplit_min << 16));
       if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
       seen.push_back(key);
       uniq.push_back(t);
@@ -2887,11 +3149,18 @@ extern "C" sg2v_status sg2v_autotune(const sg2v_plan *plan, const sg2v_graph *g,
   }
   sg2v_tuning_t best = base;
   double best_ms = 1e300;
-  // one untimed count, then the median of three timed ones
+  // one untimed count, then the median of three timed ones; a candidate whose
+  // untimed count takes over three times the best median so far is dropped
   auto time_one = [&](const sg2v_tuning_t &t, double *ms) -> sg2v_status {
     ST_TRY(sg2v_set_tuning(&t));
     double cf;
+    auto w0 = std::chrono::steady_clock::now();
     ST_TRY(sg2v_count(plan, g, c, mode, stream, nullptr, nullptr, nullptr, &cf, nullptr));
+    const double first = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+    if (first > 3.0 * best_ms) {
+      *ms = first;
+      return SG2V_OK;
+    }
     double v[3];
     for (double &x : v) {
       auto t0 = std::chrono::steady_clock::now();
