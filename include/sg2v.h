@@ -332,8 +332,11 @@ sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n_plans,
  * respect to every directed CSR weight A_G(i,j) (entry e of col_idx):
  *   grad_w[e] = df / dA_G(i,j).
  * The derivative with respect to the weight of an undirected edge is the sum
- * over its two directed entries.  Tables of each split are recomputed during
- * the backward sweep instead of being stored.
+ * over its two directed entries.  The forward tables the backward sweep reads
+ * are kept from one forward pass per colouring when they fit (half of the free
+ * device memory, or the tuning's budget); otherwise each split recomputes a
+ * forward pass up to itself instead of storing them (SG2V_TUNE_GRAD_RECOMPUTE
+ * forces that).  Both give the same gradients.
  *   grad_colorful : host, n_colorings doubles.
  *   grad_w        : device, nnz doubles, written.
  * mode: SG2V_FP64, or SG2V_FP32S (FP32 tables, forward and adjoint, each
@@ -414,6 +417,10 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
                                       instead of parallel graph branches with a workspace each */
 #define SG2V_TUNE_ROOT_THREAD 256 /* narrow root tables read by one thread per vertex from global
                                      memory instead of staged in LDS a tile of rows at a time */
+#define SG2V_TUNE_GRAD_RECOMPUTE 2048 /* sg2v_count_grad: recompute the forward tables up to each
+                                        split instead of keeping them from one forward pass per
+                                        colouring (the default when they fit half the free
+                                        device memory or the budget) */
 #define SG2V_TUNE_SPMM_PANEL 1024 /* SpMM over row panels with column-sorted entries (the
                                      CSC-Split layout of Alg. 6): up to 32 consecutive tasks per
                                      panel, the panel's entries sorted by neighbour, one wave per

@@ -2452,6 +2452,33 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
 // after both are brought to the larger exponent (k_scale_add).  The forward
 // tables are recomputed in FP32S and their frame exponents read back; the
 // per-entry gradient accumulates in FP64.
+// Forward tables for the adjoint sweep (checkpointing).  When every table the
+// sweep reads -- each split's active and passive tables and each passive
+// child's aggregation -- fits the memory budget (the tuning's budget, else half
+// of the free device memory), one forward pass per colouring keeps them all;
+// otherwise each split recomputes a forward pass up to itself, as before.
+PassOpts keep_every(const Plan &P) {
+  PassOpts o;
+  o.no_fuse = true;
+  for (size_t q = 0; q < P.nodes.size(); ++q) {
+    const Node &nd = P.nodes[q];
+    if (nd.size > 1 && P.root_index[q] < 0) o.keep.push_back({(int)q, 0});
+    if (nd.n_passive_uses > 0) o.keep.push_back({(int)q, 1});
+  }
+  return o;
+}
+
+bool keep_all_fits(const Plan &P, const sg2v_graph *g, int dt, int G, const PassOpts &every) {
+  const sg2v_tuning_t tu = tuning();
+  if (tu.flags & SG2V_TUNE_GRAD_RECOMPUTE) return false;
+  PassPlan pp;
+  build_pass(P, g->n, 1, dt, G, g->n_slots, pp, every);
+  size_t fr = 0, tot = 0;
+  (void)hipMemGetInfo(&fr, &tot);
+  const double budget = tu.budget_bytes > 0 ? (double)tu.budget_bytes : 0.5 * (double)fr;
+  return (double)pp.arena <= budget;
+}
+
 sg2v_status count_grad_fp32s(const sg2v_plan *plan, sg2v_graph *gg, const sg2v_colorings *c,
                              const double *grad_colorful, double *grad_w, hipStream_t s) {
   const Plan &P = plan->p;
@@ -2523,8 +2550,18 @@ sg2v_status count_grad_fp32s(const sg2v_plan *plan, sg2v_graph *gg, const sg2v_c
   };
 
   std::vector<int> ebar(nn, INT_MIN);
+  const PassOpts every = keep_every(P);
+  const bool keep_all = keep_all_fits(P, g, DT_F32, G, every);
+  Ctx xa;
+  if (keep_all) ST_TRY(prepare(xa, plan, gg, c, SG2V_FP32S, 1, s, every));
   for (int j = 0; j < c->count; ++j) {
     if (grad_colorful[j] == 0.0) continue;
+    if (keep_all) {
+      ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
+      xa.j0 = j;
+      ST_TRY(run_pass(xa, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr,
+                      P.root));
+    }
     launch_fill_value(DT_F32, gbase, bbar_off / 4, 0.0, s);
     std::fill(ebar.begin(), ebar.end(), INT_MIN);
     int eg = 0;
@@ -2544,16 +2581,19 @@ sg2v_status count_grad_fp32s(const sg2v_plan *plan, sg2v_graph *gg, const sg2v_c
       if (d == INT_MIN) continue;  // zero adjoint: no contributions
       const int eq = ebar[q] + d;
       launch_fill_value(DT_F32, fq, cs, std::ldexp(1.0, -d), s);
-      PassOpts opt;
-      opt.no_fuse = true;
-      if (A.size > 1) opt.keep.push_back({nd.active, 0});
-      if (Pn.size > 1) opt.keep.push_back({nd.passive, 0});
-      opt.keep.push_back({nd.passive, 1});
-      Ctx x;
-      ST_TRY(prepare(x, plan, gg, c, SG2V_FP32S, 1, s, opt));
-      ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
-      x.j0 = j;
-      ST_TRY(run_pass(x, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr, q));
+      Ctx xr;
+      if (!keep_all) {
+        PassOpts opt;
+        opt.no_fuse = true;
+        if (A.size > 1) opt.keep.push_back({nd.active, 0});
+        if (Pn.size > 1) opt.keep.push_back({nd.passive, 0});
+        opt.keep.push_back({nd.passive, 1});
+        ST_TRY(prepare(xr, plan, gg, c, SG2V_FP32S, 1, s, opt));
+        ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
+        xr.j0 = j;
+        ST_TRY(run_pass(xr, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr, q));
+      }
+      Ctx &x = keep_all ? xa : xr;
       Tab &Bp = x.pp.B[nd.passive];
       const int64_t cp = Bp.cols;
       int EB = 0, EA = 0, EP = 0;
@@ -2780,7 +2820,17 @@ sg2v_status count_grad_stored(const sg2v_plan *plan, const sg2v_graph *g, const 
   double *bbar = (double *)(gbase + bbar_off);
   auto mbar = [&](int q) { return (double *)(gbase + off[q]); };
 
+  const PassOpts every = keep_every(P);
+  const bool keep_all = keep_all_fits(P, g, DT_F64, G, every);
+  Ctx xa;
+  if (keep_all) ST_TRY(prepare(xa, plan, gg, c, mode, 1, s, every));
   for (int j = 0; j < c->count; ++j) {
+    if (keep_all) {
+      ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
+      xa.j0 = j;
+      ST_TRY(run_pass(xa, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr,
+                      P.root));
+    }
     launch_fill_value(DT_F64, gbase, bbar_off / 8, 0.0, s);
     launch_fill_value(DT_F64, mbar(P.root), g->n * ld[P.root], grad_colorful[j], s);
     for (int q = (int)nn - 1; q >= 0; --q) {
@@ -2788,17 +2838,20 @@ sg2v_status count_grad_stored(const sg2v_plan *plan, const sg2v_graph *g, const 
       if (nd.size == 1) continue;
       const Node &A = P.nodes[nd.active];
       const Node &Pn = P.nodes[nd.passive];
-      PassOpts opt;
-      opt.no_fuse = true;
-      if (A.size > 1) opt.keep.push_back({nd.active, 0});
-      if (Pn.size > 1) opt.keep.push_back({nd.passive, 0});
-      opt.keep.push_back({nd.passive, 1});
-      Ctx x;
-      ST_TRY(prepare(x, plan, gg, c, mode, 1, s, opt));
-      ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
-      x.j0 = j;
-      ST_TRY(run_pass(x, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr,
-                      q));
+      Ctx xr;
+      if (!keep_all) {
+        PassOpts opt;
+        opt.no_fuse = true;
+        if (A.size > 1) opt.keep.push_back({nd.active, 0});
+        if (Pn.size > 1) opt.keep.push_back({nd.passive, 0});
+        opt.keep.push_back({nd.passive, 1});
+        ST_TRY(prepare(xr, plan, gg, c, mode, 1, s, opt));
+        ST_TRY(ws.result.ensure((size_t)c->count * 12 + 64));
+        xr.j0 = j;
+        ST_TRY(run_pass(xr, ws.result.p, (int *)((char *)ws.result.p + (size_t)c->count * 8), nullptr,
+                        q));
+      }
+      Ctx &x = keep_all ? xa : xr;
       Tab &Bp = x.pp.B[nd.passive];
       const int64_t cs = nd.cols, ca = A.size == 1 ? P.k : A.cols, cp = Bp.cols;
       // Mbar_a += eMA^T over the active index
