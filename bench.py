@@ -391,6 +391,9 @@ def main():
                          "round-robin to the XCD neighbour ranges); counts are identical")
     ap.add_argument("--tune-flags", type=int, default=0,
                     help="extra sg2v tuning flags for the timed FP32 steps (e.g. 1024: row-panel SpMM)")
+    ap.add_argument("--spmm-width", type=int, default=0, help="SpMM chunk columns (0: automatic)")
+    ap.add_argument("--xsplit-min", type=int, default=0,
+                    help="neighbour-range split task threshold (0: automatic, 512)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch-workload", action="store_true",
                     help="skip the multi-template batch and adjoint measurements")
@@ -468,9 +471,11 @@ def main():
         return sg.count(plan, g, c, mode)
 
     # FP32 with per-column exponents
-    if args.tune_flags:
+    if args.tune_flags or args.spmm_width or args.xsplit_min:
         cur = sg.get_tuning()
         cur.flags |= args.tune_flags
+        cur.spmm_width = args.spmm_width
+        cur.xsplit_min = args.xsplit_min
         sg.restore_tuning(cur)
     for w in range(args.warmup):
         step("fp32s", 1000 + w * ncol)
@@ -542,6 +547,8 @@ def main():
             "template": "bintree15", "k": k, "colorings_per_step": ncol,
             "relabel": bool(args.relabel),
             "tune_flags": args.tune_flags,
+            "spmm_width": args.spmm_width,
+            "xsplit_min": args.xsplit_min,
             "passes_per_step": passes,
             "colorings_per_pass": ncol / passes if passes else None,
             "mode": ("fp32 mantissa + per-column exponent; one colouring per pass (a single "
