@@ -237,8 +237,8 @@ sg2v_status sg2v_colorings_download(const sg2v_colorings *c, uint8_t *out, void 
  * halved until the pass fits the device memory.  Tables of 1024 or more
  * columns run one colouring per pass: their column chunks each hold one
  * colouring's columns.
- * Errors: EINVAL (k of c differs from the plan's, U64 with weights),
- *         ENOMEM, EDEVICE. */
+ * Errors: EINVAL (k of c differs from the plan's, U64 with weights, a plan
+ *         of several templates: see sg2v_count_multi), ENOMEM, EDEVICE. */
 sg2v_status sg2v_count(const sg2v_plan *plan, const sg2v_graph *g, const sg2v_colorings *c,
                        sg2v_mode mode, void *stream, double *colorful, uint64_t *colorful_u64,
                        double *estimate, double *mean_estimate, int32_t *overflow);

@@ -298,10 +298,13 @@ int rpw_for(int64_t len, int G) {
   return r;
 }
 
-sg2v_status build_units(sg2v_graph *g, int G, hipStream_t s, UnitTable **out) {
+sg2v_status build_units(sg2v_graph *g, int G, hipStream_t s, UnitTable **out,
+                        int64_t xmin_fixed = 0) {
   // units end at the split threshold (tuning's xsplit_min, 512 neighbours by default)
   const sg2v_tuning_t tu = tuning();
-  const int64_t xmin = tu.xsplit_min > 0 ? std::min<int64_t>(tu.xsplit_min, kSegment) : kXsplitMin;
+  const int64_t xmin = xmin_fixed > 0 ? xmin_fixed
+                       : tu.xsplit_min > 0 ? std::min<int64_t>(tu.xsplit_min, kSegment)
+                                           : kXsplitMin;
   const int key = G + 64 * (int)xmin;
   auto it = g->units.find(key);
   if (it != g->units.end()) {
@@ -648,10 +651,11 @@ extern "C" sg2v_status sg2v_graph_create(int64_t n, int64_t nnz, const int64_t *
     }
   }
   ST_TRY(graph_tasks(g.get(), rp, s));
-  // task units for every row-segment width, so that counts never upload them
+  // task units for every row-segment width at the default split threshold,
+  // so that counts with the default threshold never upload them
   for (int G = 2; G <= 32; G *= 2) {
     UnitTable *U = nullptr;
-    ST_TRY(build_units(g.get(), G, s, &U));
+    ST_TRY(build_units(g.get(), G, s, &U, kXsplitMin));
   }
   *out = g.release();
   return SG2V_OK;
