@@ -2,8 +2,8 @@
 non-isomorphic tree of a given size, 47 trees of nine vertices).
 
 CPU: the enumeration (sg2v_trees) against the number of unlabelled trees
-(Cayley/Otter: 1, 1, 1, 2, 3, 6, 11, 23, 47, 106, 235, 551 for 1..12 vertices,
-19320 for 16; the paper's 47 for nine vertices) and against a brute-force
+(tests/golden/unlabelled_trees.txt: Cayley/Otter's counts for 1..16
+vertices; the paper's 47 for nine vertices) and against a brute-force
 isomorphism check written here (minimum over every root of the rooted code);
 the plan of several templates (sg2v_plan_create_multi) shares sub-templates.
 GPU: every template's count from one sg2v_count_multi call against the oracle
@@ -18,8 +18,20 @@ import graphgen as gg
 import oracle as O
 import paper_2009_11665_amd as sg
 
-UNLABELLED_TREES = {1: 1, 2: 1, 3: 1, 4: 2, 5: 3, 6: 6, 7: 11, 8: 23, 9: 47, 10: 106, 11: 235,
-                    12: 551, 16: 19320}
+def _golden_tree_counts():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "unlabelled_trees.txt")
+    out = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                t, c = line.split()
+                out[int(t)] = int(c)
+    return out
+
+
+UNLABELLED_TREES = _golden_tree_counts()
 
 
 def say(*a):
