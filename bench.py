@@ -206,9 +206,11 @@ def batch_workload(sg, gg, torch, reps=3):
     re-rooted by sg2v_template_reroot (same counts, cheaper decomposition):
     all passes of all templates recorded as one HIP graph (sg2v_count_batch,
     replayed; the templates are parallel branches of the graph), against the
-    graph with the templates in sequence, the same counts run template by
-    template, colouring included, and the templates rooted as given.  Tuning
-    from the autotuner on the widest template."""
+    graph with the templates in sequence, one persistent kernel running every
+    template's recorded launches (and the graph with that kernel's forced
+    kernel choices), the same counts run template by template, colouring
+    included, and the templates rooted as given.  Tuning from the autotuner
+    on the widest template."""
     G = gg.chung_lu_500k()
     g = sg.Graph.from_csr(G)
     given = (gg.BINTREE7, gg.PATH8, gg.CATERPILLAR10)
@@ -235,6 +237,17 @@ def batch_workload(sg, gg, torch, reps=3):
         serial.flags |= sg.TUNE_BATCH_SERIAL
         sg.restore_tuning(serial)
         t_serial, _ = graph_ms(plans)
+        # one persistent kernel over every template's launches, and the graph
+        # with the kernel choices that schedule forces (general multiply-add,
+        # vertex-order root) for a like-for-like comparison
+        pers = sg.get_tuning()
+        pers.flags = (cur.flags | sg.TUNE_BATCH_PERSISTENT) & ~sg.TUNE_SPMM_PANEL
+        sg.restore_tuning(pers)
+        t_pers, cf_pers = graph_ms(plans)
+        same = sg.get_tuning()
+        same.flags = (cur.flags | sg.TUNE_NO_COLOR_EMA | sg.TUNE_ROOT_ROWS) & ~sg.TUNE_SPMM_PANEL
+        sg.restore_tuning(same)
+        t_same, _ = graph_ms(plans)
         sg.restore_tuning(cur)
         for p, par in zip(plans, pars):  # warm
             sg.count(p, g, sg.Colorings(g, len(par), seed, ncol), "fp32s")
@@ -254,6 +267,9 @@ def batch_workload(sg, gg, torch, reps=3):
         "ms_one_graph_launch_templates_in_sequence": t_serial * 1e3,
         "ms_template_by_template": t_seq * 1e3,
         "ms_one_graph_launch_given_roots": t_given * 1e3,
+        "ms_one_persistent_kernel": t_pers * 1e3,
+        "ms_one_graph_launch_persistent_kernel_choices": t_same * 1e3,
+        "persistent_vs_graph_max_rel_diff": float(max(abs(a - b) / abs(b) for a, b in zip(cf_pers.ravel(), cf.ravel()))),
         "rerooted_vs_given_max_rel_diff": float(max(abs(a - b) / abs(b) for a, b in zip(cf.ravel(), cf_given.ravel()))),
         "parents": pars,
         "tuning": {"spmm_width": tuned.spmm_width, "ema_rows": tuned.ema_rows, "batch": tuned.batch,

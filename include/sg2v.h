@@ -421,6 +421,14 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
                                         split instead of keeping them from one forward pass per
                                         colouring (the default when they fit half the free
                                         device memory or the budget) */
+#define SG2V_TUNE_BATCH_PERSISTENT 4096 /* sg2v_count_batch: every launch of every template
+                                          recorded and run by one persistent kernel (a task
+                                          queue over the launches' blocks with a completion
+                                          counter per launch; each template's launches wait
+                                          for their predecessor) instead of a HIP graph;
+                                          implies SG2V_TUNE_NO_COLOR_EMA and
+                                          SG2V_TUNE_ROOT_ROWS, and rejects
+                                          SG2V_TUNE_SPMM_PANEL with SG2V_EINVAL */
 #define SG2V_TUNE_SPMM_PANEL 1024 /* SpMM over row panels with column-sorted entries (the
                                      CSC-Split layout of Alg. 6): up to 32 consecutive tasks per
                                      panel, the panel's entries sorted by neighbour, one wave per

@@ -453,6 +453,7 @@ TUNE_ROOT_THREAD = 256
 TUNE_BATCH_SERIAL = 512
 TUNE_SPMM_PANEL = 1024
 TUNE_GRAD_RECOMPUTE = 2048
+TUNE_BATCH_PERSISTENT = 4096
 
 
 def set_tuning(spmm_width: int = 0, ema_rows: int = 0, batch: int = 0, budget_bytes: int = 0,

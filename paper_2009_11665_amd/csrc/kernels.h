@@ -19,6 +19,22 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 
+// Block coordinates of a kernel body: the hardware's (HwBlk), or a virtual
+// block of a recorded launch run by the persistent scheduler (VBlk).
+struct HwBlk {
+  __device__ unsigned x() const { return blockIdx.x; }
+  __device__ unsigned y() const { return blockIdx.y; }
+  __device__ unsigned gx() const { return gridDim.x; }
+  __device__ unsigned gy() const { return gridDim.y; }
+};
+struct VBlk {
+  unsigned bx, by, ngx, ngy;
+  __device__ unsigned x() const { return bx; }
+  __device__ unsigned y() const { return by; }
+  __device__ unsigned gx() const { return ngx; }
+  __device__ unsigned gy() const { return ngy; }
+};
+
 template <typename T>
 constexpr bool is_u64 = std::is_same<T, uint64_t>::value;
 

@@ -2,6 +2,7 @@
 // 2009.11665) for gfx950.  Host-side launchers are at the end of the file.
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <type_traits>
 
 #include "kernels.h"
@@ -22,26 +23,23 @@ __device__ inline uint64_t fin64(uint64_t z) {
 
 // orig (nullable): caller's vertex id of each stored vertex (graphs renumbered
 // by degree), so a vertex keeps its colour under the renumbering.
-__global__ void k_color(uint8_t *__restrict__ out, int64_t n, int32_t k, uint64_t seed,
+template <class BK>
+__device__ __forceinline__ void b_color(BK bk, uint8_t *__restrict__ out, int64_t n, int32_t k, uint64_t seed,
                         int32_t first, int32_t count, const int32_t *__restrict__ orig) {
   int64_t total = n * count;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
-       x += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t x = (int64_t)bk.x() * BLOCK + threadIdx.x; x < total;
+       x += (int64_t)bk.gx() * BLOCK) {
     int64_t j = x / n, v = x - j * n;
     const uint64_t u = orig ? (uint64_t)orig[v] : (uint64_t)v;
     uint64_t h = fin64(seed ^ fin64(((uint64_t)(first + j) << 40) | u));
     out[x] = (uint8_t)(((h >> 32) * (uint64_t)k) >> 32);
   }
 }
-
-void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
-                  int32_t count, const int32_t *orig, hipStream_t s) {
-  int64_t total = n * count;
-  int64_t blocks = (total + BLOCK - 1) / BLOCK;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  k_color<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(out, n, k, seed, first, count, orig);
+__global__ void k_color(uint8_t *__restrict__ out, int64_t n, int32_t k, uint64_t seed,
+                        int32_t first, int32_t count, const int32_t *__restrict__ orig) {
+  b_color(HwBlk{}, out, n, k, seed, first, count, orig);
 }
+
 
 // out[idx[e]] = in[e] (per-entry gradients back to the caller's entry order)
 __global__ void k_scatter_f64(const double *__restrict__ in, const int64_t *__restrict__ idx,
@@ -51,12 +49,6 @@ __global__ void k_scatter_f64(const double *__restrict__ in, const int64_t *__re
     out[idx[e]] = in[e];
 }
 
-void launch_scatter_f64(const double *in, const int64_t *idx, double *out, int64_t n,
-                        hipStream_t s) {
-  if (n <= 0) return;
-  int64_t blocks = std::min<int64_t>((n + BLOCK - 1) / BLOCK, 65536);
-  k_scatter_f64<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(in, idx, out, n);
-}
 
 // ===========================================================================
 // Neighbour-colour histogram: B = A_G M_1 where M_1 is the one-hot table of a
@@ -69,11 +61,11 @@ void launch_scatter_f64(const double *in, const int64_t *idx, double *out, int64
 // counts use a ballot per colour, weighted sums a fixed-order butterfly, so
 // the result does not depend on scheduling.
 
-template <typename T, bool WEIGHTED, int D, int JG>
-__global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
+template <class BK, typename T, bool WEIGHTED, int D, int JG>
+__device__ __forceinline__ void b_hist(BK bk, const HistArgs &a) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
-  const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+  const int64_t wave = ((int64_t)bk.x() * BLOCK + threadIdx.x) / WAVE;
+  const int64_t nwaves = (int64_t)bk.gx() * WAVES_PER_BLOCK;
   T *H = (T *)a.H;
   T *Pt = (T *)a.partial;
   for (int64_t t = wave; t < a.n_tasks; t += nwaves) {
@@ -132,6 +124,10 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
       for (int64_t cidx = (int64_t)a.b * a.k + lane; cidx < a.ldh; cidx += WAVE) dst[cidx] = T(0);
   }
 }
+template <typename T, bool WEIGHTED, int D, int JG>
+__global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
+  b_hist<HwBlk, T, WEIGHTED, D, JG>(HwBlk{}, a);
+}
 
 // ===========================================================================
 // BEGIN k_spmm
@@ -150,22 +146,22 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
 // The column maximum of B (FP32S) is reduced in registers, then across the
 // block in LDS, then one atomicMax per column per block.
 
-template <typename T, int G, bool WEIGHTED, int UNR>
-__global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
+template <class BK, typename T, int G, bool WEIGHTED, int UNR>
+__device__ __forceinline__ void b_spmm(BK bk, const SpmmArgs &a) {
   constexpr int N = V16<T>::N;
   constexpr int W = G * N;
   using A = Arith<T>;
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
   const int sub = lane % G;
-  const int64_t chunk = a.chunk0 + blockIdx.y;
+  const int64_t chunk = a.chunk0 + bk.y();
   const int64_t col0 = chunk * W + sub * N;
   // Neighbour-range split of the first xunits units (the long tasks): block b
   // gathers only neighbours in range b % xsplit (workgroups go to the XCDs
   // round-robin, so each XCD's L2 serves one range) and writes a partial row
   // per task, summed in range order by k_xsplit_combine.  The other units are
   // processed whole by every block.
-  const int xr = a.xsplit ? (int)(blockIdx.x % a.xsplit) : 0;
+  const int xr = a.xsplit ? (int)(bk.x() % a.xsplit) : 0;
   // colour skipping for this chunk
   const int jb = a.chunk_jb ? a.chunk_jb[chunk] : -1;
   const uint8_t *colj = jb >= 0 ? a.colors + (int64_t)(a.j0 + jb) * a.n : nullptr;
@@ -181,8 +177,8 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
 
   for (int phase = a.xsplit ? 0 : 1; phase < 2; ++phase) {
   const bool split = phase == 0;
-  const int64_t ustart = split ? blockIdx.x / a.xsplit : a.xunits + blockIdx.x;
-  const int64_t ustep = split ? gridDim.x / a.xsplit : gridDim.x;
+  const int64_t ustart = split ? bk.x() / a.xsplit : a.xunits + bk.x();
+  const int64_t ustep = split ? bk.gx() / a.xsplit : bk.gx();
   const int64_t uend = split ? a.xunits : a.n_units;
   for (int64_t unit = ustart; unit < uend; unit += ustep) {
     const int rpw = a.unit_rpw[unit];
@@ -302,7 +298,7 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
       acc0.x[u] = x;
     }
     if (valid && stream == 0 && split) {
-      *(V16<T> *)((T *)a.partial8 + ((int64_t)xr * a.n_tasks + t) * a.ldp + (int64_t)blockIdx.y * W + sub * N) = acc0;
+      *(V16<T> *)((T *)a.partial8 + ((int64_t)xr * a.n_tasks + t) * a.ldp + (int64_t)bk.y() * W + sub * N) = acc0;
     } else if (valid && stream == 0) {
       if (slot < 0) {
         if (a.accumulate) {
@@ -347,16 +343,20 @@ __global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
     }
   }
 }
+template <typename T, int G, bool WEIGHTED, int UNR>
+__global__ void __launch_bounds__(BLOCK) k_spmm(SpmmArgs a) {
+  b_spmm<HwBlk, T, G, WEIGHTED, UNR>(HwBlk{}, a);
+}
 
 // Sum the xsplit partial rows of every task in range order: rows held in one
 // task go to B (and the column maximum), segments of long rows to their slot
 // of the long-row partial buffer.  Grid: (column vectors of the chunk group,
 // groups of tasks).
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_xsplit_combine(XsplitCombineArgs a) {
+template <class BK, typename T>
+__device__ __forceinline__ void b_xsplit_combine(BK bk, const XsplitCombineArgs &a) {
   constexpr int N = V16<T>::N;
   using A = Arith<T>;
-  const int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // vector within the group
+  const int64_t v = (int64_t)bk.x() * BLOCK + threadIdx.x;  // vector within the group
   const int64_t cl = v * N;                                       // column within the group
   if (cl >= a.ldp) return;
   const int64_t cg = a.col_first + cl;  // column of B
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(BLOCK) k_xsplit_combine(XsplitCombineArgs a) {
   T cmax[N];
 #pragma unroll
   for (int u = 0; u < N; ++u) cmax[u] = T(0);
-  for (int64_t t = blockIdx.y; t < a.n_tasks; t += gridDim.y) {
+  for (int64_t t = bk.y(); t < a.n_tasks; t += bk.gy()) {
     // the eight range partials are loaded together, then summed in range order
     V16<T> w[8];
 #pragma unroll
@@ -407,16 +407,21 @@ __global__ void __launch_bounds__(BLOCK) k_xsplit_combine(XsplitCombineArgs a) {
         atomicMax(a.mx + cg + u, __float_as_uint((float)cmax[u]));
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_xsplit_combine(XsplitCombineArgs a) {
+  b_xsplit_combine<HwBlk, T>(HwBlk{}, a);
+}
 
 // Split points of every task's neighbour list at the range boundaries
 // r * ceil(n / xs), r = 0..xs (neighbour lists are sorted).
 // bounds (nullable): xs + 1 range starts in vertex ids, else equal ranges of n / xs
-__global__ void k_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
+template <class BK>
+__device__ __forceinline__ void b_task_split(BK bk, const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
                              int64_t n_tasks, int64_t n, int xs, const int64_t *bounds,
                              uint16_t *out) {
   const int64_t span = (n + xs - 1) / xs;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_tasks * (xs + 1);
-       q += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = (int64_t)bk.x() * BLOCK + threadIdx.x; q < n_tasks * (xs + 1);
+       q += (int64_t)bk.gx() * BLOCK) {
     const int64_t t = q / (xs + 1);
     const int r = (int)(q - t * (xs + 1));
     const int32_t *c = col_idx + task_beg[t];
@@ -429,14 +434,19 @@ __global__ void k_task_split(const int32_t *col_idx, const int64_t *task_beg, co
     out[q] = (uint16_t)lo;
   }
 }
+__global__ void k_task_split(const int32_t *col_idx, const int64_t *task_beg, const int32_t *task_len,
+                             int64_t n_tasks, int64_t n, int xs, const int64_t *bounds,
+                             uint16_t *out) {
+  b_task_split(HwBlk{}, col_idx, task_beg, task_len, n_tasks, n, xs, bounds, out);
+}
 
 // Sum the partial rows of long rows in slot order, write them to B and fold
 // them into the column maximum.  Grid: (column vectors, groups of rows).
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
+template <class BK, typename T>
+__device__ __forceinline__ void b_spmm_combine(BK bk, const CombineArgs &a) {
   constexpr int N = V16<T>::N;
   using A = Arith<T>;
-  const int64_t vcol = (int64_t)blockIdx.x * BLOCK + threadIdx.x;  // vector column index
+  const int64_t vcol = (int64_t)bk.x() * BLOCK + threadIdx.x;  // vector column index
   const int64_t c0 = vcol * N;
   if (c0 >= a.ld) return;
   const T *P = (const T *)a.partial;
@@ -445,7 +455,7 @@ __global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
   T cmax[N];
 #pragma unroll
   for (int u = 0; u < N; ++u) cmax[u] = T(0);
-  for (int h = blockIdx.y; h < a.n_long; h += gridDim.y) {
+  for (int h = bk.y(); h < a.n_long; h += bk.gy()) {
     const int row = a.long_row[h];
     const int s0 = a.long_slot0[h], ns = a.long_nslot[h];
     V16<T> acc = *(const V16<T> *)(P + (int64_t)s0 * a.ld + c0);
@@ -473,6 +483,10 @@ __global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
       if (c0 + u < a.ncols_valid && (float)cmax[u] > 0.f)
         atomicMax(a.mx + c0 + u, __float_as_uint((float)cmax[u]));
   }
+}
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_spmm_combine(CombineArgs a) {
+  b_spmm_combine<HwBlk, T>(HwBlk{}, a);
 }
 
 // END k_spmm
@@ -630,11 +644,11 @@ __global__ void __launch_bounds__(BLOCK) k_spmm_panel(SpmmPanelArgs a) {
   }
 }
 
-template <typename T, int R, bool SCALED, bool STAGE>
-__global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
+template <class BK, typename T, int R, bool SCALED, bool STAGE>
+__device__ __forceinline__ void b_ema_general(BK bk, const EmaArgs &a) {
   using A = Arith<T>;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int j = blockIdx.y;
+  const int j = bk.y();
   const int sa = a.Ca | 1, sb = a.Cb | 1;  // odd row strides in LDS
   T *la = (T *)smem;
   T *lb = la + (STAGE ? R * sa : 0);
@@ -650,7 +664,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
   if (track)
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) lmx[c] = 0.f;
   const int64_t ntiles = (a.n + R - 1) / R;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int64_t tile = bk.x(); tile < ntiles; tile += bk.gx()) {
     const int64_t r0 = tile * R;
     if constexpr (STAGE) {
       __syncthreads();
@@ -737,21 +751,30 @@ __global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
     __syncthreads();
     for (int c = threadIdx.x; c < a.Cs; c += BLOCK) {
       if (track && lmx[c] > 0.f) atomicMax(a.mx + (int64_t)j * a.Cs + c, __float_as_uint(lmx[c]));
-      if (blockIdx.x == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
+      if (bk.x() == 0) a.es[(int64_t)j * a.Cs + c] = a.Ea[j] + a.Eb[j];
     }
   }
+}
+template <typename T, int R, bool SCALED, bool STAGE>
+__global__ void __launch_bounds__(BLOCK) k_ema_general(EmaArgs a) {
+  b_ema_general<HwBlk, T, R, SCALED, STAGE>(HwBlk{}, a);
 }
 
 // Colour of every CSR entry's neighbour, per colouring of the pass, so that
 // the SpMM reads it alongside col_idx instead of gathering it.
-__global__ void k_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *colors,
+template <class BK>
+__device__ __forceinline__ void b_nbr_colors(BK bk, const int32_t *col_idx, int64_t nnz, const uint8_t *colors,
                              int64_t n, int32_t j0, uint8_t *nbr) {
-  const int jj = blockIdx.y;
+  const int jj = bk.y();
   const uint8_t *col = colors + (int64_t)(j0 + jj) * n;
   uint8_t *out = nbr + (int64_t)jj * nnz;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
-       e += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t e = (int64_t)bk.x() * BLOCK + threadIdx.x; e < nnz;
+       e += (int64_t)bk.gx() * BLOCK)
     out[e] = col[col_idx[e]];
+}
+__global__ void k_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *colors,
+                             int64_t n, int32_t j0, uint8_t *nbr) {
+  b_nbr_colors(HwBlk{}, col_idx, nnz, colors, n, j0, nbr);
 }
 
 // Rows grouped by colour for the colour-restricted multiply-add.
@@ -973,8 +996,8 @@ __global__ void __launch_bounds__(NT) k_ema_colour(EmaColourArgs a) {
 // contiguous; eight elements' loads (colour, drop index, B entry) are in
 // flight per thread.  Also the adjoint's B-bar(i, P) = M-bar(i, P + col(i))
 // (drop = the plan's add table).
-template <typename T, bool SCALED>
-__global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
+template <class BK, typename T, bool SCALED>
+__device__ __forceinline__ void b_ema_single(BK bk, const EmaArgs &a) {
   constexpr int U = 8;
   extern __shared__ __align__(16) unsigned char smem[];
   const bool track = SCALED && a.mx != nullptr;
@@ -1004,7 +1027,7 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
   // and ld / W (input or output columns over output columns) is at most 20
   const int ldb32 = (int)a.ldb, lds32 = (int)a.lds;
   const int djj = dcc / a.Cs, dcl = dcc - djj * a.Cs;
-  for (int64_t i0 = (int64_t)blockIdx.x * R; i0 < a.n; i0 += (int64_t)gridDim.x * R) {
+  for (int64_t i0 = (int64_t)bk.x() * R; i0 < a.n; i0 += (int64_t)bk.gx() * R) {
     const int nrow = (int)min<int64_t>(R, a.n - i0);
     const int E = nrow * W;  // below 2^31: R * W <= 4 * U * BLOCK + W
     __syncthreads();  // previous tile's colours consumed
@@ -1073,9 +1096,13 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
     __syncthreads();
     for (int c = threadIdx.x; c < W; c += BLOCK) {
       if (track && lmx[c]) atomicMax(a.mx + c, lmx[c]);
-      if (blockIdx.x == 0) a.es[c] = a.Eb[c / a.Cs];
+      if (bk.x() == 0) a.es[c] = a.Eb[c / a.Cs];
     }
   }
+}
+template <typename T, bool SCALED>
+__global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
+  b_ema_single<HwBlk, T, SCALED>(HwBlk{}, a);
 }
 
 // FP32S column maxima of a single-vertex-active split, bounded without a pass
@@ -1083,9 +1110,10 @@ __global__ void __launch_bounds__(BLOCK) k_ema_single(EmaArgs a) {
 // colour c in C, so max_i M_s(i, C) <= max over c in C of mx_B(C \ c) f_B(C \ c)
 // (an upper bound suffices for the frame exponent).  One thread per
 // (colouring, output column).
-__global__ void k_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b, const unsigned *mxB,
+template <class BK>
+__device__ __forceinline__ void b_single_bound(BK bk, const int32_t *drop, int k, int Cs, int Cb, int b, const unsigned *mxB,
                                const float *fb, unsigned *mx) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t q = (int64_t)bk.x() * BLOCK + threadIdx.x;
   if (q >= (int64_t)b * Cs) return;
   const int jj = (int)(q / Cs), C = (int)(q - (int64_t)jj * Cs);
   float m = 0.f;
@@ -1094,6 +1122,10 @@ __global__ void k_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b
     if (d >= 0) m = fmaxf(m, __uint_as_float(mxB[(int64_t)jj * Cb + d]) * fb[(int64_t)jj * Cb + d]);
   }
   mx[q] = __float_as_uint(m);
+}
+__global__ void k_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b, const unsigned *mxB,
+                               const float *fb, unsigned *mx) {
+  b_single_bound(HwBlk{}, drop, k, Cs, Cb, b, mxB, fb, mx);
 }
 
 // ===========================================================================
@@ -1104,14 +1136,14 @@ __global__ void k_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b
 // mantissas in FP32S) and accumulated over rows in double (uint64 in U64).
 // Per-block partials are summed in block order by k_root_final.
 
-template <typename T, bool SCALED, bool HASY>
-__global__ void __launch_bounds__(BLOCK) k_root(RootArgs a) {
+template <class BK, typename T, bool SCALED, bool HASY>
+__device__ __forceinline__ void b_root(BK bk, const RootArgs &a) {
   using A = Arith<T>;
   using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
   __shared__ Acc red[WAVES_PER_BLOCK];
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
-  const int j = blockIdx.y;
+  const int j = bk.y();
   const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
   const T *X = (const T *)a.X;
   const T *Y = (const T *)a.Y;
@@ -1120,8 +1152,8 @@ __global__ void __launch_bounds__(BLOCK) k_root(RootArgs a) {
   const int2 *list = (const int2 *)a.list;
   bool ovf = false;
   Acc tot = Acc(0);
-  const int64_t wave = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wv;
-  const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+  const int64_t wave = (int64_t)bk.x() * WAVES_PER_BLOCK + wv;
+  const int64_t nwaves = (int64_t)bk.gx() * WAVES_PER_BLOCK;
   for (int64_t i = wave; i < a.n; i += nwaves) {
     const int c = col[i];
     const int2 *lc = list + (int64_t)c * a.L;
@@ -1155,19 +1187,23 @@ __global__ void __launch_bounds__(BLOCK) k_root(RootArgs a) {
       if constexpr (is_u64<Acc>) b = A::add(b, red[q], ovf);
       else b += red[q];
     }
-    ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = b;
+    ((Acc *)a.partial)[(int64_t)j * bk.gx() + bk.x()] = b;
   }
   if constexpr (is_u64<T>) {
     if (ovf) atomicOr(a.ovf, 1);
   }
+}
+template <typename T, bool SCALED, bool HASY>
+__global__ void __launch_bounds__(BLOCK) k_root(RootArgs a) {
+  b_root<HwBlk, T, SCALED, HASY>(HwBlk{}, a);
 }
 
 // Root reduction with the vertex's rows staged in LDS (multiplied by the
 // column factors in FP32S): one block per row at a time, threads stride over
 // the colour's list, a fixed-order reduction gives the row value, which is
 // accumulated over the block's rows in double (uint64 in U64).
-template <typename T, bool SCALED, bool HASY>
-__global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
+template <class BK, typename T, bool SCALED, bool HASY>
+__device__ __forceinline__ void b_root_lds(BK bk, const RootArgs &a) {
   using A = Arith<T>;
   using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1176,7 +1212,7 @@ __global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
   T *ly = (HASY && !a.same_xy) ? lx + a.Cx : lx;
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x / WAVE;
-  const int j = blockIdx.y;
+  const int j = bk.y();
   const uint8_t *col = a.colors + (int64_t)(a.j0 + j) * a.n;
   const T *X = (const T *)a.X;
   const T *Y = (const T *)a.Y;
@@ -1184,7 +1220,7 @@ __global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
   const float *fy = (SCALED && HASY) ? a.fy + (int64_t)j * a.Cy : nullptr;
   bool ovf = false;
   Acc tot = Acc(0);
-  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+  for (int64_t i = bk.x(); i < a.n; i += bk.gx()) {
     __syncthreads();
     const T *xr = X + i * a.ldx + (int64_t)j * a.Cx;
     for (int c = threadIdx.x; c < a.Cx; c += BLOCK) {
@@ -1227,10 +1263,14 @@ __global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
       else tot += (double)r;
     }
   }
-  if (threadIdx.x == 0) ((Acc *)a.partial)[(int64_t)j * gridDim.x + blockIdx.x] = tot;
+  if (threadIdx.x == 0) ((Acc *)a.partial)[(int64_t)j * bk.gx() + bk.x()] = tot;
   if constexpr (is_u64<T>) {
     if (ovf) atomicOr(a.ovf, 1);
   }
+}
+template <typename T, bool SCALED, bool HASY>
+__global__ void __launch_bounds__(BLOCK) k_root_lds(RootArgs a) {
+  b_root_lds<HwBlk, T, SCALED, HASY>(HwBlk{}, a);
 }
 
 // Root reduction, colour by colour: block b takes the contiguous vertex
@@ -1531,9 +1571,9 @@ __global__ void __launch_bounds__(BLOCK) k_root_stage(RootArgs a, int R, int lgx
   }
 }
 
-template <typename Acc>
-__global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+template <class BK, typename Acc>
+__device__ __forceinline__ void b_root_final(BK bk, const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
+  const int j = bk.x() * 64 + threadIdx.x;
   if (j >= b) return;
   Acc s = partial[(int64_t)j * nblk];
   bool o = false;
@@ -1547,17 +1587,26 @@ __global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int 
   out[j] = s;
   if (o) atomicOr(ovf, 1);
 }
+template <typename Acc>
+__global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
+  b_root_final<HwBlk, Acc>(HwBlk{}, partial, nblk, b, out, ovf);
+}
 
 // Column maxima of an FP32S table (float bits, atomicMax), for producers too
 // wide to keep them in LDS.  Grid: (column vectors, row groups).
-__global__ void __launch_bounds__(BLOCK) k_colmax(const float *X, int64_t n, int64_t ld, int64_t cols,
+template <class BK>
+__device__ __forceinline__ void b_colmax(BK bk, const float *X, int64_t n, int64_t ld, int64_t cols,
                                                    unsigned *mx) {
-  const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t c = (int64_t)bk.x() * BLOCK + threadIdx.x;
   if (c >= cols) return;
-  const int64_t r0 = (int64_t)blockIdx.y * n / gridDim.y, r1 = (int64_t)(blockIdx.y + 1) * n / gridDim.y;
+  const int64_t r0 = (int64_t)bk.y() * n / bk.gy(), r1 = (int64_t)(bk.y() + 1) * n / bk.gy();
   float m = 0.f;
   for (int64_t i = r0; i < r1; ++i) m = fmaxf(m, X[i * ld + c]);
   if (m > 0.f) atomicMax(mx + c, __float_as_uint(m));
+}
+__global__ void __launch_bounds__(BLOCK) k_colmax(const float *X, int64_t n, int64_t ld, int64_t cols,
+                                                   unsigned *mx) {
+  b_colmax(HwBlk{}, X, n, ld, cols, mx);
 }
 
 // ===========================================================================
@@ -1567,8 +1616,9 @@ __global__ void __launch_bounds__(BLOCK) k_colmax(const float *X, int64_t n, int
 //   f[c] = 2^(e[c] - E[j])                          (exact power of two)
 // so that consumers read X(i, c) * f[c] <= 1 in the common frame 2^E[j].
 
-__global__ void k_norm_prep(const int *e, const unsigned *mx, int C, float *f, int *E) {
-  const int j = blockIdx.x;
+template <class BK>
+__device__ __forceinline__ void b_norm_prep(BK bk, const int *e, const unsigned *mx, int C, float *f, int *E) {
+  const int j = bk.x();
   __shared__ int red[BLOCK];
   int best = INT_MIN;
   for (int c = threadIdx.x; c < C; c += BLOCK) {
@@ -1588,33 +1638,52 @@ __global__ void k_norm_prep(const int *e, const unsigned *mx, int C, float *f, i
   }
   if (threadIdx.x == 0) E[j] = Ej;
 }
+__global__ void k_norm_prep(const int *e, const unsigned *mx, int C, float *f, int *E) {
+  b_norm_prep(HwBlk{}, e, mx, C, f, E);
+}
 
-__global__ void k_root_exp(const int *EX, const int *EY, int *out, int b) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+template <class BK>
+__device__ __forceinline__ void b_root_exp(BK bk, const int *EX, const int *EY, int *out, int b) {
+  const int j = bk.x() * 64 + threadIdx.x;
   if (j < b) out[j] = EX[j] + (EY ? EY[j] : 0);
 }
-
-__global__ void k_fill_u32(unsigned *p, int64_t n, unsigned v) {
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
-       x += (int64_t)gridDim.x * blockDim.x)
-    p[x] = v;
+__global__ void k_root_exp(const int *EX, const int *EY, int *out, int b) {
+  b_root_exp(HwBlk{}, EX, EY, out, b);
 }
 
-__global__ void k_copy_i32(const int *src, int *dst, int64_t n) {
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
-       x += (int64_t)gridDim.x * blockDim.x)
+template <class BK>
+__device__ __forceinline__ void b_fill_u32(BK bk, unsigned *p, int64_t n, unsigned v) {
+  for (int64_t x = (int64_t)bk.x() * BLOCK + threadIdx.x; x < n;
+       x += (int64_t)bk.gx() * BLOCK)
+    p[x] = v;
+}
+__global__ void k_fill_u32(unsigned *p, int64_t n, unsigned v) {
+  b_fill_u32(HwBlk{}, p, n, v);
+}
+
+template <class BK>
+__device__ __forceinline__ void b_copy_i32(BK bk, const int *src, int *dst, int64_t n) {
+  for (int64_t x = (int64_t)bk.x() * BLOCK + threadIdx.x; x < n;
+       x += (int64_t)bk.gx() * BLOCK)
     dst[x] = src[x];
+}
+__global__ void k_copy_i32(const int *src, int *dst, int64_t n) {
+  b_copy_i32(HwBlk{}, src, dst, n);
 }
 
 // zero the padding columns [c_from, ld) of a row-major table
-template <typename T>
-__global__ void k_zero_pad(T *X, int64_t n, int64_t ld, int64_t c_from) {
+template <class BK, typename T>
+__device__ __forceinline__ void b_zero_pad(BK bk, T *X, int64_t n, int64_t ld, int64_t c_from) {
   const int64_t w = ld - c_from;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n * w;
-       x += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t x = (int64_t)bk.x() * BLOCK + threadIdx.x; x < n * w;
+       x += (int64_t)bk.gx() * BLOCK) {
     const int64_t i = x / w, c = c_from + (x - i * w);
     X[i * ld + c] = T(0);
   }
+}
+template <typename T>
+__global__ void k_zero_pad(T *X, int64_t n, int64_t ld, int64_t c_from) {
+  b_zero_pad<HwBlk, T>(HwBlk{}, X, n, ld, c_from);
 }
 
 // ===========================================================================
@@ -1672,11 +1741,302 @@ __global__ void k_scale_add(float *Y, int64_t ldy, const float *X, int64_t ldx, 
   }
 }
 
+template <class BK, typename T>
+__device__ __forceinline__ void b_fill_value(BK bk, T *X, int64_t count, T v) {
+  for (int64_t x = (int64_t)bk.x() * BLOCK + threadIdx.x; x < count;
+       x += (int64_t)bk.gx() * BLOCK)
+    X[x] = v;
+}
 template <typename T>
 __global__ void k_fill_value(T *X, int64_t count, T v) {
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count;
-       x += (int64_t)gridDim.x * blockDim.x)
-    X[x] = v;
+  b_fill_value<HwBlk, T>(HwBlk{}, X, count, v);
+}
+
+// ===========================================================================
+// Persistent schedule: one kernel runs the recorded launches of several
+// independent chains (the templates of a batch).  Every virtual block of a
+// recorded launch is a task; a block of k_persist takes the next ticket,
+// waits (thread 0, bounded by a wall-clock limit) until the predecessor of
+// the ticket's launch in its chain has completed all of its tasks, runs the
+// launch's kernel body with the virtual block coordinates, and counts the
+// task as done.  Tickets are ordered so that every predecessor launch has
+// smaller tickets, and a ticket is only taken by a running block, so every
+// wait ends (by induction over the tickets) whatever the number of resident
+// blocks.  Ordering across the XCDs: each thread's writes are released at
+// agent scope (L2 write-back) before the done counter is incremented, and a
+// block that has waited acquires at agent scope (L2 invalidate) before it
+// reads; a block remembers per chain the latest predecessor it has seen
+// complete, so it waits and acquires once per launch boundary.
+
+// argument blocks of the launchers with scalar parameters
+struct ColorPA {
+  uint8_t *out;
+  int64_t n;
+  int32_t k, first, count, pad;
+  uint64_t seed;
+  const int32_t *orig;
+};
+struct FillPA {
+  unsigned *p;
+  int64_t n;
+  unsigned v;
+};
+struct CopyPA {
+  const int *src;
+  int *dst;
+  int64_t n;
+};
+struct NbrColPA {
+  const int32_t *col_idx;
+  int64_t nnz;
+  const uint8_t *colors;
+  int64_t n;
+  int32_t j0;
+  uint8_t *nbr;
+};
+struct ColmaxPA {
+  const float *X;
+  int64_t n, ld, cols;
+  unsigned *mx;
+};
+struct NormPrepPA {
+  const int *e;
+  const unsigned *mx;
+  int C;
+  float *f;
+  int *E;
+};
+struct RootExpPA {
+  const int *EX, *EY;
+  int *out;
+  int b;
+};
+struct SingleBoundPA {
+  const int32_t *drop;
+  int k, Cs, Cb, b;
+  const unsigned *mxB;
+  const float *fb;
+  unsigned *mx;
+};
+struct TaskSplitPA {
+  const int32_t *col_idx;
+  const int64_t *task_beg;
+  const int32_t *task_len;
+  int64_t n_tasks, n;
+  int xs;
+  const int64_t *bounds;
+  uint16_t *out;
+};
+struct RootFinalPA {
+  const void *partial;
+  int nblk, b;
+  void *out;
+  int *ovf;
+};
+struct ZeroPadPA {
+  void *X;
+  int64_t n, ld, c_from;
+};
+
+enum PBody : int32_t {
+  PB_COLOR = 0,
+  PB_FILL_U32,
+  PB_COPY_I32,
+  PB_NBR_COLORS,
+  PB_COLMAX,
+  PB_NORM_PREP,
+  PB_ROOT_EXP,
+  PB_SINGLE_BOUND,
+  PB_TASK_SPLIT,
+  PB_XSPLIT_COMBINE,
+  PB_SPMM_COMBINE,
+  PB_EMA_SINGLE,
+  PB_ROOT_FINAL,
+  PB_ZERO_PAD,
+  PB_HIST,                           // + 2 * weighted + (b > 1)
+  PB_ROOT = PB_HIST + 4,             // + (Y present)
+  PB_ROOT_LDS = PB_ROOT + 2,         // + (Y present)
+  PB_EMA_GENERAL = PB_ROOT_LDS + 2,  // + 2 * log2(R) + staged
+  PB_SPMM = PB_EMA_GENERAL + 10,     // + 4 * log2(G / 2) + 2 * weighted + (8 gathers in flight)
+  PB_COUNT = PB_SPMM + 20
+};
+
+#define P_EMA(ri, R)                                                                   \
+  case PB_EMA_GENERAL + 2 * ri:                                                        \
+    b_ema_general<VBlk, T, R, SC, false>(bk, *(const EmaArgs *)A);                     \
+    break;                                                                             \
+  case PB_EMA_GENERAL + 2 * ri + 1:                                                    \
+    b_ema_general<VBlk, T, R, SC, true>(bk, *(const EmaArgs *)A);                      \
+    break;
+#define P_SPMM(gi, G)                                                                  \
+  case PB_SPMM + 4 * gi:                                                               \
+    b_spmm<VBlk, T, G, false, 4>(bk, *(const SpmmArgs *)A);                            \
+    break;                                                                             \
+  case PB_SPMM + 4 * gi + 1:                                                           \
+    b_spmm<VBlk, T, G, false, 8>(bk, *(const SpmmArgs *)A);                            \
+    break;                                                                             \
+  case PB_SPMM + 4 * gi + 2:                                                           \
+    b_spmm<VBlk, T, G, true, 4>(bk, *(const SpmmArgs *)A);                             \
+    break;                                                                             \
+  case PB_SPMM + 4 * gi + 3:                                                           \
+    b_spmm<VBlk, T, G, true, 8>(bk, *(const SpmmArgs *)A);                             \
+    break;
+
+template <typename T>
+__device__ __forceinline__ void p_run(int body, const unsigned char *A, const VBlk &bk) {
+  constexpr bool SC = std::is_same<T, float>::value;
+  using Acc = typename std::conditional<is_u64<T>, uint64_t, double>::type;
+  switch (body) {
+    case PB_COLOR: {
+      const ColorPA &q = *(const ColorPA *)A;
+      b_color(bk, q.out, q.n, q.k, q.seed, q.first, q.count, q.orig);
+    } break;
+    case PB_FILL_U32: {
+      const FillPA &q = *(const FillPA *)A;
+      b_fill_u32(bk, q.p, q.n, q.v);
+    } break;
+    case PB_COPY_I32: {
+      const CopyPA &q = *(const CopyPA *)A;
+      b_copy_i32(bk, q.src, q.dst, q.n);
+    } break;
+    case PB_NBR_COLORS: {
+      const NbrColPA &q = *(const NbrColPA *)A;
+      b_nbr_colors(bk, q.col_idx, q.nnz, q.colors, q.n, q.j0, q.nbr);
+    } break;
+    case PB_COLMAX: {
+      const ColmaxPA &q = *(const ColmaxPA *)A;
+      b_colmax(bk, q.X, q.n, q.ld, q.cols, q.mx);
+    } break;
+    case PB_NORM_PREP: {
+      const NormPrepPA &q = *(const NormPrepPA *)A;
+      b_norm_prep(bk, q.e, q.mx, q.C, q.f, q.E);
+    } break;
+    case PB_ROOT_EXP: {  // a 64-thread kernel
+      const RootExpPA &q = *(const RootExpPA *)A;
+      if (threadIdx.x < 64) b_root_exp(bk, q.EX, q.EY, q.out, q.b);
+    } break;
+    case PB_SINGLE_BOUND: {
+      const SingleBoundPA &q = *(const SingleBoundPA *)A;
+      b_single_bound(bk, q.drop, q.k, q.Cs, q.Cb, q.b, q.mxB, q.fb, q.mx);
+    } break;
+    case PB_TASK_SPLIT: {
+      const TaskSplitPA &q = *(const TaskSplitPA *)A;
+      b_task_split(bk, q.col_idx, q.task_beg, q.task_len, q.n_tasks, q.n, q.xs, q.bounds, q.out);
+    } break;
+    case PB_XSPLIT_COMBINE:
+      b_xsplit_combine<VBlk, T>(bk, *(const XsplitCombineArgs *)A);
+      break;
+    case PB_SPMM_COMBINE:
+      b_spmm_combine<VBlk, T>(bk, *(const CombineArgs *)A);
+      break;
+    case PB_EMA_SINGLE:
+      b_ema_single<VBlk, T, SC>(bk, *(const EmaArgs *)A);
+      break;
+    case PB_ROOT_FINAL: {  // a 64-thread kernel
+      const RootFinalPA &q = *(const RootFinalPA *)A;
+      if (threadIdx.x < 64) b_root_final<VBlk, Acc>(bk, (const Acc *)q.partial, q.nblk, q.b, (Acc *)q.out, q.ovf);
+    } break;
+    case PB_ZERO_PAD: {
+      const ZeroPadPA &q = *(const ZeroPadPA *)A;
+      b_zero_pad<VBlk, T>(bk, (T *)q.X, q.n, q.ld, q.c_from);
+    } break;
+    case PB_HIST:
+      b_hist<VBlk, T, false, 4, 1>(bk, *(const HistArgs *)A);
+      break;
+    case PB_HIST + 1:
+      b_hist<VBlk, T, false, 2, 4>(bk, *(const HistArgs *)A);
+      break;
+    case PB_HIST + 2:
+      b_hist<VBlk, T, true, 4, 1>(bk, *(const HistArgs *)A);
+      break;
+    case PB_HIST + 3:
+      b_hist<VBlk, T, true, 2, 4>(bk, *(const HistArgs *)A);
+      break;
+    case PB_ROOT:
+      b_root<VBlk, T, SC, false>(bk, *(const RootArgs *)A);
+      break;
+    case PB_ROOT + 1:
+      b_root<VBlk, T, SC, true>(bk, *(const RootArgs *)A);
+      break;
+    case PB_ROOT_LDS:
+      b_root_lds<VBlk, T, SC, false>(bk, *(const RootArgs *)A);
+      break;
+    case PB_ROOT_LDS + 1:
+      b_root_lds<VBlk, T, SC, true>(bk, *(const RootArgs *)A);
+      break;
+    P_EMA(0, 1)
+    P_EMA(1, 2)
+    P_EMA(2, 4)
+    P_EMA(3, 8)
+    P_EMA(4, 16)
+    P_SPMM(0, 2)
+    P_SPMM(1, 4)
+    P_SPMM(2, 8)
+    P_SPMM(3, 16)
+    P_SPMM(4, 32)
+    default:
+      break;
+  }
+}
+#undef P_EMA
+#undef P_SPMM
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) k_persist(PersistArgs p) {
+  __shared__ long long s_t;
+  __shared__ int s_cur, s_acq;
+  __shared__ int s_seen[kPMaxChains];  // per chain: latest predecessor seen complete (thread 0)
+  for (int c = threadIdx.x; c < p.n_chain; c += BLOCK) s_seen[c] = -1;
+  int cur0 = 0;  // thread 0: launch of the block's last ticket (tickets only grow)
+  for (;;) {
+    __syncthreads();  // the previous task's reads of s_t, s_cur and s_acq are done
+    if (threadIdx.x == 0) {
+      long long t = -1;
+      int acq = 0;
+      if (__hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        const unsigned long long q = atomicAdd(p.next, 1ull);
+        if ((long long)q < p.total) t = (long long)q;
+      }
+      if (t >= 0) {
+        while (cur0 + 1 < p.n_launch && p.L[cur0 + 1].first <= t) ++cur0;
+        const int pred = p.L[cur0].pred;
+        const int ch = p.L[cur0].chain;
+        if (pred >= 0 && s_seen[ch] < pred) {
+          const unsigned need = (unsigned)p.L[pred].ntask;
+          const long long t0 = wall_clock64();
+          while (__hip_atomic_load(p.done + pred, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (__hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                (uint64_t)(wall_clock64() - t0) > p.timeout) {
+              atomicOr(p.err, 1);
+              t = -1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+          }
+          if (t >= 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_seen[ch] = pred;
+            acq = 1;
+          }
+        }
+      }
+      s_t = t;
+      s_cur = cur0;
+      s_acq = acq;
+    }
+    __syncthreads();
+    const long long t = s_t;
+    if (t < 0) break;  // uniform: every thread read s_t after the barrier
+    if (s_acq) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int cur = s_cur;
+    const PLaunch &L = p.L[cur];
+    const long long vb = t - L.first;
+    const VBlk bk{(unsigned)(vb % L.gx), (unsigned)(vb / L.gx), L.gx, L.gy};
+    p_run<T>(L.body, L.args, bk);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(p.done + cur, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ===========================================================================
@@ -1685,6 +2045,57 @@ __global__ void k_fill_value(T *X, int64_t count, T v) {
 static inline unsigned grid_cap(int64_t want, int64_t cap) {
   if (want < 1) want = 1;
   return (unsigned)(want < cap ? want : cap);
+}
+
+thread_local PRecorder *t_prec = nullptr;
+
+// append a launch to the recorder of this thread
+template <typename A>
+static void prec_add(int body, int dtype, const A &args, dim3 grid, size_t lds) {
+  static_assert(sizeof(A) <= kPArgBytes, "argument block larger than PLaunch::args");
+  static_assert(std::is_trivially_copyable<A>::value, "argument block must be plain data");
+  PRecord r;
+  r.body = body;
+  r.dtype = dtype;
+  r.chain = t_prec->chain;
+  r.gx = grid.x;
+  r.gy = grid.y;
+  r.lds = lds;
+  std::memset(r.args, 0, sizeof(r.args));
+  std::memcpy(r.args, &args, sizeof(A));
+  if (grid.z != 1 && t_prec->err.empty()) t_prec->err = "a launch with a 3-D grid";
+  t_prec->rec.push_back(r);
+}
+
+static void prec_reject(const char *what) {
+  if (t_prec->err.empty()) t_prec->err = what;
+}
+
+static int log2i(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+void launch_color(uint8_t *out, int64_t n, int32_t k, uint64_t seed, int32_t first,
+                  int32_t count, const int32_t *orig, hipStream_t s) {
+  int64_t total = n * count;
+  int64_t blocks = (total + BLOCK - 1) / BLOCK;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  if (t_prec) {
+    prec_add(PB_COLOR, -1, ColorPA{out, n, k, first, count, 0, seed, orig}, dim3((unsigned)blocks), 0);
+    return;
+  }
+  k_color<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(out, n, k, seed, first, count, orig);
+}
+
+void launch_scatter_f64(const double *in, const int64_t *idx, double *out, int64_t n,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  if (t_prec) return prec_reject("launch_scatter_f64");
+  int64_t blocks = std::min<int64_t>((n + BLOCK - 1) / BLOCK, 65536);
+  k_scatter_f64<<<dim3((unsigned)blocks), dim3(BLOCK), 0, s>>>(in, idx, out, n);
 }
 
 template <typename T>
@@ -1701,6 +2112,7 @@ static void hist_dispatch(const HistArgs &a, int blocks, hipStream_t s) {
 }
 
 void launch_hist(int dtype, const HistArgs &a, int blocks, hipStream_t s) {
+  if (t_prec) return prec_add(PB_HIST + (a.w ? 2 : 0) + (a.b == 1 ? 0 : 1), dtype, a, dim3(blocks), 0);
   if (dtype == DT_F32) hist_dispatch<float>(a, blocks, s);
   else if (dtype == DT_F64) hist_dispatch<double>(a, blocks, s);
   else hist_dispatch<uint64_t>(a, blocks, s);
@@ -1725,6 +2137,11 @@ static int spmm_t(const SpmmArgs &a, int G, dim3 grid, hipStream_t s) {
 }
 
 int launch_spmm(int dtype, const SpmmArgs &a, int G, int unroll, dim3 grid, hipStream_t s) {
+  if (t_prec) {
+    if (G != 2 && G != 4 && G != 8 && G != 16 && G != 32) return -1;
+    prec_add(PB_SPMM + 4 * (log2i(G) - 1) + (a.w ? 2 : 0) + (unroll == 8 ? 1 : 0), dtype, a, grid, 0);
+    return 0;
+  }
   if (unroll == 8) {
     if (dtype == DT_F32) return spmm_t<float, 8>(a, G, grid, s);
     if (dtype == DT_F64) return spmm_t<double, 8>(a, G, grid, s);
@@ -1755,6 +2172,10 @@ static int panel_t(const SpmmPanelArgs &a, int G, dim3 grid, hipStream_t s) {
 }
 
 int launch_spmm_panel(int dtype, const SpmmPanelArgs &a, int G, dim3 grid, hipStream_t s) {
+  if (t_prec) {
+    prec_reject("the row-panel SpMM");
+    return 0;
+  }
   if (dtype == DT_F32) return panel_t<float>(a, G, grid, s);
   if (dtype == DT_F64) return panel_t<double>(a, G, grid, s);
   return panel_t<uint64_t>(a, G, grid, s);
@@ -1764,6 +2185,7 @@ void launch_xsplit_combine(int dtype, const XsplitCombineArgs &a, hipStream_t s)
   const int N = (dtype == DT_F32) ? 4 : 2;
   const int64_t nvec = (a.ldp + N - 1) / N;
   dim3 grid(grid_cap((nvec + BLOCK - 1) / BLOCK, 1 << 20), grid_cap((a.n_tasks + 63) / 64, 8192));
+  if (t_prec) return prec_add(PB_XSPLIT_COMBINE, dtype, a, grid, 0);
   if (dtype == DT_F32) k_xsplit_combine<float><<<grid, BLOCK, 0, s>>>(a);
   else if (dtype == DT_F64) k_xsplit_combine<double><<<grid, BLOCK, 0, s>>>(a);
   else k_xsplit_combine<uint64_t><<<grid, BLOCK, 0, s>>>(a);
@@ -1774,6 +2196,9 @@ void launch_task_split(const int32_t *col_idx, const int64_t *task_beg, const in
                        hipStream_t s) {
   const int64_t total = n_tasks * (xs + 1);
   if (total == 0) return;
+  if (t_prec)
+    return prec_add(PB_TASK_SPLIT, -1, TaskSplitPA{col_idx, task_beg, task_len, n_tasks, n, xs, bounds, out},
+                    dim3(grid_cap((total + BLOCK - 1) / BLOCK, 65536)), 0);
   k_task_split<<<grid_cap((total + BLOCK - 1) / BLOCK, 65536), BLOCK, 0, s>>>(col_idx, task_beg, task_len,
                                                                             n_tasks, n, xs, bounds, out);
 }
@@ -1783,6 +2208,7 @@ void launch_spmm_combine(int dtype, const CombineArgs &a, hipStream_t s) {
   const int64_t nvec = (a.ld + N - 1) / N;
   dim3 grid(grid_cap((nvec + BLOCK - 1) / BLOCK, 1 << 20), grid_cap((a.n_long + 31) / 32, 4096));
   if (a.n_long == 0) return;
+  if (t_prec) return prec_add(PB_SPMM_COMBINE, dtype, a, grid, 0);
   if (dtype == DT_F32) k_spmm_combine<float><<<grid, BLOCK, 0, s>>>(a);
   else if (dtype == DT_F64) k_spmm_combine<double><<<grid, BLOCK, 0, s>>>(a);
   else k_spmm_combine<uint64_t><<<grid, BLOCK, 0, s>>>(a);
@@ -1809,6 +2235,11 @@ static int ema_g_r(const EmaArgs &a, int R, dim3 grid, size_t lds, hipStream_t s
 
 int launch_ema_general(int dtype, const EmaArgs &a, int R, bool stage, dim3 grid, size_t lds,
                        hipStream_t s) {
+  if (t_prec) {
+    if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16) return -1;
+    prec_add(PB_EMA_GENERAL + 2 * log2i(R) + (stage ? 1 : 0), dtype, a, grid, lds);
+    return 0;
+  }
   if (dtype == DT_F32)
     return stage ? ema_g_r<float, true, true>(a, R, grid, lds, s)
                  : ema_g_r<float, true, false>(a, R, grid, lds, s);
@@ -1825,6 +2256,7 @@ void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipSt
   const int64_t R = std::max<int64_t>(1, (4 * 8 * BLOCK) / W);
   const size_t total = (lds ? (lds + 15) / 16 * 16 : 0) + (a.kc ? ((size_t)a.kc * a.Cs * 2 + 15) / 16 * 16 : 0) +
                        ((size_t)R * a.nb + 15) / 16 * 16;
+  if (t_prec) return prec_add(PB_EMA_SINGLE, dtype, a, grid, total);
   auto go = [&](auto kern) {
     if (total > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total);
     kern<<<grid, BLOCK, total, s>>>(a);
@@ -1836,6 +2268,7 @@ void launch_ema_single(int dtype, const EmaArgs &a, dim3 grid, size_t lds, hipSt
 
 void launch_root(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) {
   const bool hy = a.Y != nullptr;
+  if (t_prec) return prec_add(PB_ROOT + (hy ? 1 : 0), dtype, a, grid, 0);
   if (dtype == DT_F32) {
     if (hy) k_root<float, true, true><<<grid, BLOCK, 0, s>>>(a);
     else k_root<float, true, false><<<grid, BLOCK, 0, s>>>(a);
@@ -1875,12 +2308,14 @@ static void root_stage_t(const RootArgs &a, dim3 grid, int R, size_t lds, hipStr
 }
 
 void launch_root_stage(int dtype, const RootArgs &a, dim3 grid, int R, size_t lds, hipStream_t s) {
+  if (t_prec) return prec_reject("the staged-row root reduction");
   if (dtype == DT_F32) root_stage_t<float, true>(a, grid, R, lds, s);
   else if (dtype == DT_F64) root_stage_t<double, false>(a, grid, R, lds, s);
   else root_stage_t<uint64_t, false>(a, grid, R, lds, s);
 }
 
 void launch_root_thread(int dtype, const RootArgs &a, dim3 grid, hipStream_t s) {
+  if (t_prec) return prec_reject("the thread-per-vertex root reduction");
   if (dtype == DT_F32) root_thread_t<float, true>(a, grid, s);
   else if (dtype == DT_F64) root_thread_t<double, false>(a, grid, s);
   else root_thread_t<uint64_t, false>(a, grid, s);
@@ -1897,12 +2332,14 @@ static void root_tile_t(const RootArgs &a, dim3 grid, size_t lds, bool db, hipSt
 }
 
 void launch_root_tile(int dtype, const RootArgs &a, dim3 grid, size_t lds, bool db, hipStream_t s) {
+  if (t_prec) return prec_reject("the colour-by-colour root reduction");
   if (dtype == DT_F32) root_tile_t<float, true>(a, grid, lds, db, s);
   else if (dtype == DT_F64) root_tile_t<double, false>(a, grid, lds, db, s);
   else root_tile_t<uint64_t, false>(a, grid, lds, db, s);
 }
 
 void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+  if (t_prec) return prec_add(PB_ROOT_LDS + (a.Y ? 1 : 0), dtype, a, grid, lds);
   if (dtype == DT_F32) root_lds_t<float, true>(a, grid, lds, s);
   else if (dtype == DT_F64) root_lds_t<double, false>(a, grid, lds, s);
   else root_lds_t<uint64_t, false>(a, grid, lds, s);
@@ -1912,6 +2349,7 @@ void launch_root_final(int dtype, const void *partial, int nblk, int b, void *ou
                        hipStream_t s) {
   // one thread per colouring of the pass
   const unsigned blocks = (unsigned)((b + 63) / 64);
+  if (t_prec) return prec_add(PB_ROOT_FINAL, dtype, RootFinalPA{partial, nblk, b, out, ovf}, dim3(blocks), 0);
   if (dtype == DT_U64)
     k_root_final<uint64_t><<<blocks, 64, 0, s>>>((const uint64_t *)partial, nblk, b, (uint64_t *)out, ovf);
   else
@@ -1921,12 +2359,16 @@ void launch_root_final(int dtype, const void *partial, int nblk, int b, void *ou
 void launch_nbr_colors(const int32_t *col_idx, int64_t nnz, const uint8_t *colors, int64_t n,
                        int32_t j0, int32_t b, uint8_t *nbr, hipStream_t s) {
   if (nnz == 0) return;
+  if (t_prec)
+    return prec_add(PB_NBR_COLORS, -1, NbrColPA{col_idx, nnz, colors, n, j0, nbr},
+                    dim3(grid_cap((nnz + BLOCK - 1) / BLOCK, 16384), b), 0);
   k_nbr_colors<<<dim3(grid_cap((nnz + BLOCK - 1) / BLOCK, 16384), b), BLOCK, 0, s>>>(col_idx, nnz, colors, n, j0, nbr);
 }
 
 void launch_bucket(const uint8_t *colors, int64_t n, int32_t j0, int32_t b, int32_t k, int32_t *counts,
                    int32_t *cursor, int32_t *perm, hipStream_t s) {
   const unsigned g = grid_cap((n + BLOCK - 1) / BLOCK, 1024);
+  if (t_prec) return prec_reject("the colour bucketing of the colour-restricted multiply-add");
   k_fill_u32<<<grid_cap((2 * b * k + BLOCK - 1) / BLOCK, 64), BLOCK, 0, s>>>((unsigned *)counts, (int64_t)b * k, 0u);
   k_fill_u32<<<grid_cap((2 * b * k + BLOCK - 1) / BLOCK, 64), BLOCK, 0, s>>>((unsigned *)cursor, (int64_t)b * k, 0u);
   k_bucket_count<<<dim3(g, b), BLOCK, 0, s>>>(colors, n, j0, k, counts);
@@ -1957,6 +2399,10 @@ static int ema_colour_t(const EmaColourArgs &a, int R, int nt, dim3 grid, size_t
 }
 
 int launch_ema_colour(int dtype, const EmaColourArgs &a, int R, int nt, dim3 grid, size_t lds, hipStream_t s) {
+  if (t_prec) {
+    prec_reject("the colour-restricted multiply-add");
+    return 0;
+  }
   if (dtype == DT_F32) return ema_colour_t<float, true>(a, R, nt, grid, lds, s);
   if (dtype == DT_F64) return ema_colour_t<double, false>(a, R, nt, grid, lds, s);
   return ema_colour_t<uint64_t, false>(a, R, nt, grid, lds, s);
@@ -1966,36 +2412,43 @@ void launch_colmax(const float *X, int64_t n, int64_t ld, int64_t cols, unsigned
   if (n == 0 || cols == 0) return;
   const int64_t gx = (cols + BLOCK - 1) / BLOCK;
   const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, (4096 + gx - 1) / gx));
+  if (t_prec) return prec_add(PB_COLMAX, -1, ColmaxPA{X, n, ld, cols, mx}, dim3((unsigned)gx, (unsigned)gy), 0);
   k_colmax<<<dim3((unsigned)gx, (unsigned)gy), BLOCK, 0, s>>>(X, n, ld, cols, mx);
 }
 
 void launch_norm_prep(const int *e, const unsigned *mx, int C, int b, float *f, int *E,
                       hipStream_t s) {
+  if (t_prec) return prec_add(PB_NORM_PREP, -1, NormPrepPA{e, mx, C, f, E}, dim3(b), 0);
   k_norm_prep<<<b, BLOCK, 0, s>>>(e, mx, C, f, E);
 }
 
 void launch_root_exp(const int *EX, const int *EY, int *out, int b, hipStream_t s) {
+  if (t_prec) return prec_add(PB_ROOT_EXP, -1, RootExpPA{EX, EY, out, b}, dim3((b + 63) / 64), 0);
   k_root_exp<<<(b + 63) / 64, 64, 0, s>>>(EX, EY, out, b);
 }
 
 void launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t s) {
   if (n <= 0) return;
+  if (t_prec) return prec_add(PB_FILL_U32, -1, FillPA{p, n, v}, dim3(grid_cap((n + BLOCK - 1) / BLOCK, 4096)), 0);
   k_fill_u32<<<grid_cap((n + BLOCK - 1) / BLOCK, 4096), BLOCK, 0, s>>>(p, n, v);
 }
 
 void launch_copy_i32(const int *src, int *dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;
+  if (t_prec) return prec_add(PB_COPY_I32, -1, CopyPA{src, dst, n}, dim3(grid_cap((n + BLOCK - 1) / BLOCK, 4096)), 0);
   k_copy_i32<<<grid_cap((n + BLOCK - 1) / BLOCK, 4096), BLOCK, 0, s>>>(src, dst, n);
 }
 
 void launch_scale_add(float *Y, int64_t ldy, const float *X, int64_t ldx, int64_t n, int64_t cols, float so,
                       float sn, hipStream_t s) {
   if (n == 0 || cols == 0) return;
+  if (t_prec) return prec_reject("launch_scale_add");
   k_scale_add<<<grid_cap((n * cols + BLOCK - 1) / BLOCK, 65536), BLOCK, 0, s>>>(Y, ldy, X, ldx, n, cols, so, sn);
 }
 
 void launch_sddmm(int dtype, const SddmmArgs &a, hipStream_t s) {
   const unsigned g = grid_cap((a.n + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 4096);
+  if (t_prec) return prec_reject("launch_sddmm");
   if (dtype == DT_F64) k_sddmm<double><<<g, BLOCK, 0, s>>>(a);
   else if (dtype == DT_F32) k_sddmm<float><<<g, BLOCK, 0, s>>>(a);
 }
@@ -2004,12 +2457,16 @@ void launch_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b, cons
                          const float *fb, unsigned *mx, hipStream_t s) {
   const int64_t total = (int64_t)b * Cs;
   if (total == 0) return;
+  if (t_prec)
+    return prec_add(PB_SINGLE_BOUND, -1, SingleBoundPA{drop, k, Cs, Cb, b, mxB, fb, mx},
+                    dim3(grid_cap((total + BLOCK - 1) / BLOCK, 1 << 20)), 0);
   k_single_bound<<<grid_cap((total + BLOCK - 1) / BLOCK, 1 << 20), BLOCK, 0, s>>>(drop, k, Cs, Cb, b, mxB, fb,
                                                                                  mx);
 }
 
 void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t s) {
   if (count <= 0) return;
+  if (t_prec) return prec_reject("launch_fill_value");
   const unsigned g = grid_cap((count + BLOCK - 1) / BLOCK, 65536);
   if (dtype == DT_F64) k_fill_value<double><<<g, BLOCK, 0, s>>>((double *)X, count, v);
   else if (dtype == DT_F32) k_fill_value<float><<<g, BLOCK, 0, s>>>((float *)X, count, (float)v);
@@ -2019,9 +2476,31 @@ void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t 
 void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, hipStream_t s) {
   if (c_from >= ld || n == 0) return;
   const unsigned g = grid_cap((n * (ld - c_from) + BLOCK - 1) / BLOCK, 65536);
+  if (t_prec) return prec_add(PB_ZERO_PAD, dtype, ZeroPadPA{X, n, ld, c_from}, dim3(g), 0);
   if (dtype == DT_F32) k_zero_pad<float><<<g, BLOCK, 0, s>>>((float *)X, n, ld, c_from);
   else if (dtype == DT_F64) k_zero_pad<double><<<g, BLOCK, 0, s>>>((double *)X, n, ld, c_from);
   else k_zero_pad<uint64_t><<<g, BLOCK, 0, s>>>((uint64_t *)X, n, ld, c_from);
+}
+
+template <typename T>
+static int persist_occ(size_t lds) {
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void *)k_persist<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<T>, BLOCK, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+int persist_blocks_per_cu(int dtype, size_t lds) {
+  if (dtype == DT_F32) return persist_occ<float>(lds);
+  if (dtype == DT_F64) return persist_occ<double>(lds);
+  return persist_occ<uint64_t>(lds);
+}
+
+void launch_persist(int dtype, const PersistArgs &a, unsigned blocks, size_t lds, hipStream_t s) {
+  if (dtype == DT_F32) k_persist<float><<<blocks, BLOCK, lds, s>>>(a);
+  else if (dtype == DT_F64) k_persist<double><<<blocks, BLOCK, lds, s>>>(a);
+  else k_persist<uint64_t><<<blocks, BLOCK, lds, s>>>(a);
 }
 
 }  // namespace sg2v

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 namespace sg2v {
 
 enum DType { DT_F64 = 0, DT_F32 = 1, DT_U64 = 2 };
@@ -281,5 +284,60 @@ void launch_fill_value(int dtype, void *X, int64_t count, double v, hipStream_t 
 void launch_single_bound(const int32_t *drop, int k, int Cs, int Cb, int b, const unsigned *mxB,
                          const float *fb, unsigned *mx, hipStream_t s);
 void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Persistent schedule.  While t_prec is set on a thread, the launchers above
+// append their launch (kernel body, grid, dynamic LDS and a copy of the
+// arguments) to it instead of issuing it; k_persist then runs the recorded
+// launches of several independent chains (one per template) in one kernel:
+// each virtual block of a launch is a task, tasks are handed out in ticket
+// order, and a task waits until its launch's predecessor in the same chain has
+// completed all of its tasks (a per-launch counter).  Launches that cannot run
+// there (other block sizes, multi-kernel launchers) set `err`.
+
+constexpr int kPArgBytes = 320;   // largest argument block (static_assert in kernels.hip)
+constexpr int kPMaxChains = 256;
+
+struct PLaunch {
+  int32_t body;   // kernel body (PBody in kernels.hip)
+  int32_t chain;
+  int32_t pred;   // launch that must complete before this one starts (-1: none)
+  uint32_t gx, gy;
+  uint32_t pad;
+  int64_t first;  // ticket of the first virtual block
+  int64_t ntask;  // gx * gy
+  alignas(16) unsigned char args[kPArgBytes];
+};
+
+struct PRecord {
+  int32_t body = 0;
+  int32_t dtype = -1;  // element type of a typed body, -1 for untyped ones
+  int32_t chain = 0;
+  uint32_t gx = 1, gy = 1;
+  size_t lds = 0;
+  unsigned char args[kPArgBytes];
+};
+
+struct PRecorder {
+  int32_t chain = 0;
+  std::vector<PRecord> rec;
+  std::string err;  // first launch that cannot be recorded
+};
+extern thread_local PRecorder *t_prec;
+
+struct PersistArgs {
+  const PLaunch *L;
+  int32_t n_launch;
+  int32_t n_chain;
+  int64_t total;             // tickets (virtual blocks of all launches)
+  unsigned *done;            // per launch: virtual blocks completed
+  unsigned long long *next;  // ticket counter
+  int *err;                  // set when a wait exceeded `timeout`
+  uint64_t timeout;          // wall-clock ticks a dependency wait may take
+};
+
+// blocks of k_persist<dtype> one CU holds with `lds` bytes of dynamic LDS
+int persist_blocks_per_cu(int dtype, size_t lds);
+void launch_persist(int dtype, const PersistArgs &a, unsigned blocks, size_t lds, hipStream_t s);
 
 }  // namespace sg2v

@@ -49,10 +49,22 @@ namespace {
 sg2v_tuning_t g_tune = {0, 0, 0, 0, 0, 0, 0, 0};
 std::mutex g_tune_mu;
 
+// flags a call forces for its own duration (the persistent batch schedule
+// runs only kernels with 256-thread blocks)
+thread_local int32_t t_tune_or = 0;
+
 sg2v_tuning_t tuning() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  return g_tune;
+  sg2v_tuning_t t = g_tune;
+  t.flags |= t_tune_or;
+  return t;
 }
+
+struct TuneOr {
+  int32_t old;
+  explicit TuneOr(int32_t f) : old(t_tune_or) { t_tune_or |= f; }
+  ~TuneOr() { t_tune_or = old; }
+};
 
 constexpr int64_t kSegment = 4096;  // neighbours per SpMM task (longer rows are split)
 constexpr int kPersistBlocks = 2048;
@@ -2199,6 +2211,29 @@ namespace {
 // One captured multi-template count: colourings of every plan plus all of
 // their passes, instantiated once and replayed while the workspace buffers
 // it captured are unchanged.
+// Recorded launches of a batch run by one k_persist launch: the host copy of
+// the launch table (in ticket order) and its device copy, the per-launch done
+// counters, the ticket counter and the error flag.
+struct PSched {
+  int dtype = 0;
+  int n_chain = 1;
+  size_t lds = 0;
+  unsigned blocks = 0;
+  int64_t total = 0;
+  uint64_t timeout = 0;
+  std::vector<PLaunch> h;
+  PLaunch *d = nullptr;
+  unsigned *ctl = nullptr;  // done[n] | ticket counter (8 bytes, aligned) | error flag
+  size_t ctl_words = 0;
+  ~PSched() {
+    if (d) (void)hipFree(d);
+    if (ctl) (void)hipFree(ctl);
+  }
+  unsigned *done() const { return ctl; }
+  unsigned long long *next() const { return (unsigned long long *)(ctl + ((h.size() + 1) & ~(size_t)1)); }
+  int *err() const { return (int *)(ctl + ((h.size() + 1) & ~(size_t)1) + 2); }
+};
+
 struct BatchGraph {
   std::vector<const sg2v_plan *> plans;
   const sg2v_graph *g = nullptr;
@@ -2211,6 +2246,7 @@ struct BatchGraph {
   std::vector<std::unique_ptr<Workspace>> wss;
   bool conc = false;
   hipGraphExec_t exec = nullptr;
+  std::unique_ptr<PSched> ps;  // persistent schedule instead of the graph
   int device = -1;
   ~BatchGraph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -2225,6 +2261,110 @@ bool same_tuning(const sg2v_tuning_t &a, const sg2v_tuning_t &b) {
          a.flags == b.flags && a.budget_bytes == b.budget_bytes &&
          a.xsplit_group == b.xsplit_group && a.launch_chunks == b.launch_chunks &&
          a.xsplit_min == b.xsplit_min;
+}
+
+// Ticket order of the recorded launches: each chain's launches in order, a
+// launch's start estimated as its predecessor's start plus the predecessor's
+// rounds of resident blocks, launches sorted by that start (ties by chain),
+// so that independent chains interleave and every predecessor precedes its
+// successors.
+sg2v_status build_psched(const PRecorder &rec, int dtype, int n_chain, int device, PSched *ps) {
+  const size_t n = rec.rec.size();
+  if (n == 0) {
+    set_error("sg2v_count_batch: nothing was recorded for the persistent schedule");
+    return SG2V_EINVAL;
+  }
+  if (n_chain > kPMaxChains) {
+    set_error("sg2v_count_batch: the persistent schedule runs at most %d templates", kPMaxChains);
+    return SG2V_EINVAL;
+  }
+  size_t lds = 0;
+  for (const PRecord &r : rec.rec) {
+    if (r.dtype >= 0 && r.dtype != dtype) {
+      set_error("sg2v_count_batch: a recorded launch has another element type");
+      return SG2V_EINVAL;
+    }
+    lds = std::max(lds, r.lds);
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  const int per_cu = persist_blocks_per_cu(dtype, lds);
+  if (per_cu < 1) {
+    set_error("sg2v_count_batch: the persistent kernel does not fit a CU with %zu bytes of LDS", lds);
+    return SG2V_ENOMEM;
+  }
+  const int64_t resident = (int64_t)prop.multiProcessorCount * per_cu;
+  std::vector<double> start(n);
+  std::vector<int> prev(n, -1), last(n_chain, -1);
+  for (size_t i = 0; i < n; ++i) {
+    const PRecord &r = rec.rec[i];
+    const int c = r.chain;
+    if (last[c] >= 0) {
+      const PRecord &q = rec.rec[last[c]];
+      const double rounds = std::ceil((double)q.gx * q.gy / (double)resident);
+      start[i] = start[last[c]] + std::max(1.0, rounds);
+      prev[i] = last[c];
+    } else {
+      start[i] = 0.0;
+    }
+    last[c] = (int)i;
+  }
+  std::vector<int> order(n);
+  for (size_t i = 0; i < n; ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (start[a] != start[b]) return start[a] < start[b];
+    return rec.rec[a].chain < rec.rec[b].chain;
+  });
+  std::vector<int> pos(n);
+  for (size_t q = 0; q < n; ++q) pos[order[q]] = (int)q;
+  ps->h.assign(n, PLaunch{});
+  int64_t first = 0;
+  for (size_t q = 0; q < n; ++q) {
+    const PRecord &r = rec.rec[order[q]];
+    PLaunch &L = ps->h[q];
+    std::memset(&L, 0, sizeof(L));
+    L.body = r.body;
+    L.chain = r.chain;
+    L.pred = prev[order[q]] >= 0 ? pos[prev[order[q]]] : -1;
+    L.gx = r.gx;
+    L.gy = r.gy;
+    L.first = first;
+    L.ntask = (int64_t)r.gx * r.gy;
+    std::memcpy(L.args, r.args, kPArgBytes);
+    if (L.pred >= (int)q || L.ntask < 1 || L.ntask > (int64_t)UINT32_MAX) {
+      set_error("sg2v_count_batch: inconsistent persistent schedule");
+      return SG2V_EINVAL;
+    }
+    first += L.ntask;
+  }
+  int clock_khz = 0;
+  if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz <= 0)
+    clock_khz = 100000;
+  ps->dtype = dtype;
+  ps->n_chain = n_chain;
+  ps->lds = lds;
+  ps->blocks = (unsigned)std::min<int64_t>(resident, first);
+  ps->total = first;
+  ps->timeout = (uint64_t)clock_khz * 1000ull * 30ull;  // 30 s per dependency wait
+  HIP_TRY(hipMalloc((void **)&ps->d, n * sizeof(PLaunch)));
+  HIP_TRY(hipMemcpy(ps->d, ps->h.data(), n * sizeof(PLaunch), hipMemcpyHostToDevice));
+  ps->ctl_words = ((n + 1) & ~(size_t)1) + 4;
+  HIP_TRY(hipMalloc((void **)&ps->ctl, ps->ctl_words * 4));
+  return SG2V_OK;
+}
+
+void run_psched(const PSched &ps, hipStream_t s) {
+  launch_fill_u32(ps.ctl, (int64_t)ps.ctl_words, 0u, s);
+  PersistArgs a{};
+  a.L = ps.d;
+  a.n_launch = (int32_t)ps.h.size();
+  a.n_chain = ps.n_chain;
+  a.total = ps.total;
+  a.done = ps.done();
+  a.next = ps.next();
+  a.err = ps.err();
+  a.timeout = ps.timeout;
+  launch_persist(ps.dtype, a, ps.blocks, ps.lds, s);
 }
 
 void ws_gens(Workspace &ws, uint64_t *out) {
@@ -2285,6 +2425,10 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
   // its own, when those fit in half of the free device memory (estimated from
   // the pass plan of each); otherwise one after another in the shared one.
   const sg2v_tuning_t tune = tuning();
+  const bool persist = (tune.flags & SG2V_TUNE_BATCH_PERSISTENT) != 0;
+  // the persistent schedule runs kernels of 256-thread blocks only: the
+  // general multiply-add and the vertex-order root reduction
+  TuneOr forced(persist ? (SG2V_TUNE_NO_COLOR_EMA | SG2V_TUNE_ROOT_ROWS) : 0);
   bool conc = n_plans > 1 && !(tune.flags & SG2V_TUNE_BATCH_SERIAL);
   if (conc) {
     size_t fr = 0, tot = 0;
@@ -2365,64 +2509,95 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
       xs[p].ovf = (int *)ws.ovf.p;
       ST_TRY(bind_tables(xs[p]));
     }
-    hipStream_t cs = nullptr;
-    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    // one stream (and one join event) per template for the parallel branches
-    std::vector<hipStream_t> sp(n_plans, cs);
-    std::vector<hipEvent_t> done(n_plans, nullptr);
-    hipEvent_t fork = nullptr;
-    hipError_t he = hipSuccess;
-    if (conc) {
-      he = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-      for (int p = 0; p < n_plans && he == hipSuccess; ++p) {
-        he = hipStreamCreateWithFlags(&sp[p], hipStreamNonBlocking);
-        if (he == hipSuccess) he = hipEventCreateWithFlags(&done[p], hipEventDisableTiming);
-      }
-    }
-    hipGraph_t graph = nullptr;
-    sg2v_status st = SG2V_OK;
-    if (he == hipSuccess) he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (he == hipSuccess) {
+    if (persist) {
+      // record every launch of every template (one chain each when they have
+      // workspaces of their own) for one k_persist launch
+      PRecorder rec;
+      sg2v_status st = SG2V_OK;
+      t_prec = &rec;
       t_capturing = true;
-      launch_fill_u32((unsigned *)ws.ovf.p, 1, 0u, cs);
-      if (conc) he = hipEventRecord(fork, cs);
-      for (int p = 0; p < n_plans && st == SG2V_OK && he == hipSuccess; ++p) {
-        if (conc) he = hipStreamWaitEvent(sp[p], fork, 0);
-        if (he != hipSuccess) break;
-        launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, g->orig_id, sp[p]);
-        xs[p].s = sp[p];
+      for (int p = 0; p < n_plans && st == SG2V_OK; ++p) {
+        rec.chain = conc ? p : 0;
+        launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, g->orig_id, us);
+        xs[p].s = us;
         xs[p].c = bg->cols[p].get();
         st = enqueue_count(xs[p], ncol, bs[p], res + (size_t)p * ncol * 8, Ed + (size_t)p * ncol);
-        if (conc && st == SG2V_OK) {
-          he = hipEventRecord(done[p], sp[p]);
-          if (he == hipSuccess) he = hipStreamWaitEvent(cs, done[p], 0);
-        }
       }
       t_capturing = false;
-      hipError_t he2 = hipStreamEndCapture(cs, &graph);
-      if (he == hipSuccess) he = he2;
-    }
-    if (he == hipSuccess && st == SG2V_OK) he = hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (conc) {
-      for (int p = 0; p < n_plans; ++p) {
-        if (sp[p] && sp[p] != cs) (void)hipStreamDestroy(sp[p]);
-        if (done[p]) (void)hipEventDestroy(done[p]);
+      t_prec = nullptr;
+      if (st != SG2V_OK) return st;
+      if (!rec.err.empty()) {
+        set_error("sg2v_count_batch: %s cannot run in the persistent schedule", rec.err.c_str());
+        return SG2V_EINVAL;
       }
-      if (fork) (void)hipEventDestroy(fork);
-    }
-    (void)hipStreamDestroy(cs);
-    if (st != SG2V_OK) return st;
-    if (he != hipSuccess) {
-      set_error("sg2v_count_batch: graph capture failed: %s", hipGetErrorString(he));
-      return SG2V_EDEVICE;
+      bg->ps.reset(new PSched());
+      ST_TRY(build_psched(rec, dt, conc ? n_plans : 1, dev, bg->ps.get()));
+    } else {
+      hipStream_t cs = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      // one stream (and one join event) per template for the parallel branches
+      std::vector<hipStream_t> sp(n_plans, cs);
+      std::vector<hipEvent_t> done(n_plans, nullptr);
+      hipEvent_t fork = nullptr;
+      hipError_t he = hipSuccess;
+      if (conc) {
+        he = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int p = 0; p < n_plans && he == hipSuccess; ++p) {
+          he = hipStreamCreateWithFlags(&sp[p], hipStreamNonBlocking);
+          if (he == hipSuccess) he = hipEventCreateWithFlags(&done[p], hipEventDisableTiming);
+        }
+      }
+      hipGraph_t graph = nullptr;
+      sg2v_status st = SG2V_OK;
+      if (he == hipSuccess) he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (he == hipSuccess) {
+        t_capturing = true;
+        launch_fill_u32((unsigned *)ws.ovf.p, 1, 0u, cs);
+        if (conc) he = hipEventRecord(fork, cs);
+        for (int p = 0; p < n_plans && st == SG2V_OK && he == hipSuccess; ++p) {
+          if (conc) he = hipStreamWaitEvent(sp[p], fork, 0);
+          if (he != hipSuccess) break;
+          launch_color(bg->cols[p]->d, g->n, plans[p]->p.k, seed, 0, ncol, g->orig_id, sp[p]);
+          xs[p].s = sp[p];
+          xs[p].c = bg->cols[p].get();
+          st = enqueue_count(xs[p], ncol, bs[p], res + (size_t)p * ncol * 8, Ed + (size_t)p * ncol);
+          if (conc && st == SG2V_OK) {
+            he = hipEventRecord(done[p], sp[p]);
+            if (he == hipSuccess) he = hipStreamWaitEvent(cs, done[p], 0);
+          }
+        }
+        t_capturing = false;
+        hipError_t he2 = hipStreamEndCapture(cs, &graph);
+        if (he == hipSuccess) he = he2;
+      }
+      if (he == hipSuccess && st == SG2V_OK) he = hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (conc) {
+        for (int p = 0; p < n_plans; ++p) {
+          if (sp[p] && sp[p] != cs) (void)hipStreamDestroy(sp[p]);
+          if (done[p]) (void)hipEventDestroy(done[p]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+      }
+      (void)hipStreamDestroy(cs);
+      if (st != SG2V_OK) return st;
+      if (he != hipSuccess) {
+        set_error("sg2v_count_batch: graph capture failed: %s", hipGetErrorString(he));
+        return SG2V_EDEVICE;
+      }
     }
     ws_gens(ws, bg->gens);
     g_batch_cache.push_back(std::move(bg));
     if (g_batch_cache.size() > 8) g_batch_cache.erase(g_batch_cache.begin());
     hit = g_batch_cache.back().get();
   }
-  HIP_TRY(hipGraphLaunch(hit->exec, us));
+  if (hit->ps) {
+    launch_fill_u32((unsigned *)ws.ovf.p, 1, 0u, us);
+    run_psched(*hit->ps, us);
+    HIP_TRY(hipGetLastError());
+  } else {
+    HIP_TRY(hipGraphLaunch(hit->exec, us));
+  }
   std::vector<double> rf((size_t)n_plans * ncol);
   std::vector<uint64_t> ru((size_t)n_plans * ncol);
   std::vector<int> E((size_t)n_plans * ncol, 0);
@@ -2430,7 +2605,13 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
                          (size_t)n_plans * ncol * 8, hipMemcpyDeviceToHost, us));
   if (dt == DT_F32)
     HIP_TRY(hipMemcpyAsync(E.data(), Ed, (size_t)n_plans * ncol * 4, hipMemcpyDeviceToHost, us));
+  int perr = 0;
+  if (hit->ps) HIP_TRY(hipMemcpyAsync(&perr, hit->ps->err(), 4, hipMemcpyDeviceToHost, us));
   HIP_TRY(hipStreamSynchronize(us));
+  if (perr) {
+    set_error("sg2v_count_batch: a dependency wait of the persistent schedule exceeded 30 s");
+    return SG2V_EDEVICE;
+  }
   for (int p = 0; p < n_plans; ++p)
     finish_counts(plans[p]->p.roots[0], ncol, dt, rf.data() + (size_t)p * ncol, ru.data() + (size_t)p * ncol,
                   E.data() + (size_t)p * ncol, colorful ? colorful + (size_t)p * ncol : nullptr,

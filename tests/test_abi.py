@@ -218,3 +218,12 @@ def test_reroot_rejects_bad_input():
     with pytest.raises(sg.Sg2vError) as e:
         sg.reroot([-1, 0], 2, -1.0)
     assert e.value.status == -1
+
+
+def test_python_tuning_flags_match_header():
+    """The binding's SG2V_TUNE_* constants carry the header's values."""
+    txt = open(HEADER).read()
+    defs = dict(re.findall(r"#define SG2V_(TUNE_[A-Z0-9_]+)\s+(\d+)", txt))
+    assert "TUNE_BATCH_PERSISTENT" in defs
+    for name, val in defs.items():
+        assert getattr(sg, name) == int(val), name
