@@ -146,6 +146,10 @@ __global__ void __launch_bounds__(BLOCK) k_hist(HistArgs a) {
 // The column maximum of B (FP32S) is reduced in registers, then across the
 // block in LDS, then one atomicMax per column per block.
 
+// the column-maximum reduction buffer, one for every instantiation (a kernel
+// that holds several of them allocates it once)
+__shared__ float spmm_red[WAVES_PER_BLOCK][WAVE];
+
 template <class BK, typename T, int G, bool WEIGHTED, int UNR>
 __device__ __forceinline__ void b_spmm(BK bk, const SpmmArgs &a) {
   constexpr int N = V16<T>::N;
@@ -323,7 +327,6 @@ __device__ __forceinline__ void b_spmm(BK bk, const SpmmArgs &a) {
   }
   if (a.mx) {
     // lanes with equal `sub` hold the same columns
-    __shared__ float red[WAVES_PER_BLOCK][WAVE];
 #pragma unroll
     for (int u = 0; u < N; ++u) {
       float x = (float)cmax[u];
@@ -331,11 +334,11 @@ __device__ __forceinline__ void b_spmm(BK bk, const SpmmArgs &a) {
       cmax[u] = (T)x;
     }
     for (int u = 0; u < N; ++u) {
-      if (lane < G) red[wv][lane] = (float)cmax[u];
+      if (lane < G) spmm_red[wv][lane] = (float)cmax[u];
       __syncthreads();
       if (wv == 0 && lane < G) {
-        float x = red[0][lane];
-        for (int q = 1; q < WAVES_PER_BLOCK; ++q) x = fmaxf(x, red[q][lane]);
+        float x = spmm_red[0][lane];
+        for (int q = 1; q < WAVES_PER_BLOCK; ++q) x = fmaxf(x, spmm_red[q][lane]);
         const int64_t c = chunk * W + lane * N + u;
         if (c < a.ncols_valid && x > 0.f) atomicMax(a.mx + c, __float_as_uint(x));
       }
@@ -1762,11 +1765,12 @@ __global__ void k_fill_value(T *X, int64_t count, T v) {
 // task as done.  Tickets are ordered so that every predecessor launch has
 // smaller tickets, and a ticket is only taken by a running block, so every
 // wait ends (by induction over the tickets) whatever the number of resident
-// blocks.  Ordering across the XCDs: each thread's writes are released at
-// agent scope (L2 write-back) before the done counter is incremented, and a
-// block that has waited acquires at agent scope (L2 invalidate) before it
-// reads; a block remembers per chain the latest predecessor it has seen
-// complete, so it waits and acquires once per launch boundary.
+// blocks.  Ordering across the XCDs: after a task every wave waits for its
+// stores, then one agent-scope release (L2 write-back) precedes the done
+// counter's increment; a block that has waited acquires at agent scope (L1
+// and L2 invalidate) before any of its threads reads; a block remembers per
+// chain the latest predecessor it has seen complete, so it waits and
+// acquires once per launch boundary.
 
 // argument blocks of the launchers with scalar parameters
 struct ColorPA {
@@ -1984,15 +1988,14 @@ __device__ __forceinline__ void p_run(int body, const unsigned char *A, const VB
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) k_persist(PersistArgs p) {
   __shared__ long long s_t;
-  __shared__ int s_cur, s_acq;
+  __shared__ int s_cur;
   __shared__ int s_seen[kPMaxChains];  // per chain: latest predecessor seen complete (thread 0)
   for (int c = threadIdx.x; c < p.n_chain; c += BLOCK) s_seen[c] = -1;
   int cur0 = 0;  // thread 0: launch of the block's last ticket (tickets only grow)
   for (;;) {
-    __syncthreads();  // the previous task's reads of s_t, s_cur and s_acq are done
+    __syncthreads();  // the previous task's reads of s_t and s_cur are done
     if (threadIdx.x == 0) {
       long long t = -1;
-      int acq = 0;
       if (__hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
         const unsigned long long q = atomicAdd(p.next, 1ull);
         if ((long long)q < p.total) t = (long long)q;
@@ -2014,28 +2017,31 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8
             __builtin_amdgcn_s_sleep(8);
           }
           if (t >= 0) {
+            // invalidates this CU's L1 and this XCD's L2 for the whole block
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_seen[ch] = pred;
-            acq = 1;
           }
         }
       }
       s_t = t;
       s_cur = cur0;
-      s_acq = acq;
     }
     __syncthreads();
     const long long t = s_t;
     if (t < 0) break;  // uniform: every thread read s_t after the barrier
-    if (s_acq) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int cur = s_cur;
     const PLaunch &L = p.L[cur];
     const long long vb = t - L.first;
     const VBlk bk{(unsigned)(vb % L.gx), (unsigned)(vb / L.gx), L.gx, L.gy};
     p_run<T>(L.body, L.args, bk);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // every wave's stores have reached its XCD's L2 (the barrier alone does
+    // not wait for them); then one agent-scope release writes that L2 back
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(p.done + cur, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(p.done + cur, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
