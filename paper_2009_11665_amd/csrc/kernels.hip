@@ -1576,19 +1576,26 @@ __global__ void __launch_bounds__(BLOCK) k_root_stage(RootArgs a, int R, int lgx
 
 template <class BK, typename Acc>
 __device__ __forceinline__ void b_root_final(BK bk, const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
-  const int j = bk.x() * 64 + threadIdx.x;
+  // one 64-lane wave per colouring: lane l sums the partials l, l + 64, ...
+  // in order, then a fixed butterfly (the result does not depend on timing)
+  const int j = bk.x();
   if (j >= b) return;
-  Acc s = partial[(int64_t)j * nblk];
+  const int lane = threadIdx.x;
+  const Acc *pj = partial + (int64_t)j * nblk;
+  Acc s = Acc(0);
   bool o = false;
-  for (int q = 1; q < nblk; ++q) {
-    if constexpr (std::is_same<Acc, double>::value) {
-      s += partial[(int64_t)j * nblk + q];
-    } else {
-      s = Arith<uint64_t>::add(s, partial[(int64_t)j * nblk + q], o);
-    }
+  for (int q = lane; q < nblk; q += 64) {
+    if constexpr (std::is_same<Acc, double>::value) s += pj[q];
+    else s = Arith<uint64_t>::add(s, pj[q], o);
   }
-  out[j] = s;
-  if (o) atomicOr(ovf, 1);
+  for (int off = 1; off < 64; off <<= 1) {
+    if constexpr (std::is_same<Acc, double>::value) s += shfl_xor(s, off);
+    else s = Arith<uint64_t>::add(s, shfl_xor(s, off), o);
+  }
+  if (lane == 0) {
+    out[j] = s;
+    if (o) atomicOr(ovf, 1);
+  }
 }
 template <typename Acc>
 __global__ void k_root_final(const Acc *partial, int nblk, int b, Acc *out, int *ovf) {
@@ -2353,8 +2360,8 @@ void launch_root_lds(int dtype, const RootArgs &a, dim3 grid, size_t lds, hipStr
 
 void launch_root_final(int dtype, const void *partial, int nblk, int b, void *out, int *ovf,
                        hipStream_t s) {
-  // one thread per colouring of the pass
-  const unsigned blocks = (unsigned)((b + 63) / 64);
+  // one 64-thread wave per colouring of the pass
+  const unsigned blocks = (unsigned)b;
   if (t_prec) return prec_add(PB_ROOT_FINAL, dtype, RootFinalPA{partial, nblk, b, out, ovf}, dim3(blocks), 0);
   if (dtype == DT_U64)
     k_root_final<uint64_t><<<blocks, 64, 0, s>>>((const uint64_t *)partial, nblk, b, (uint64_t *)out, ovf);
