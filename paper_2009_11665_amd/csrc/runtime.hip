@@ -2208,9 +2208,6 @@ extern "C" sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph 
 
 namespace {
 
-// One captured multi-template count: colourings of every plan plus all of
-// their passes, instantiated once and replayed while the workspace buffers
-// it captured are unchanged.
 // Recorded launches of a batch run by one k_persist launch: the host copy of
 // the launch table (in ticket order) and its device copy, the per-launch done
 // counters, the ticket counter and the error flag.
@@ -2234,6 +2231,9 @@ struct PSched {
   int *err() const { return (int *)(ctl + ((h.size() + 1) & ~(size_t)1) + 2); }
 };
 
+// One captured multi-template count: colourings of every plan plus all of
+// their passes, instantiated once and replayed while the workspace buffers
+// it captured are unchanged.
 struct BatchGraph {
   std::vector<const sg2v_plan *> plans;
   const sg2v_graph *g = nullptr;
@@ -2299,6 +2299,10 @@ sg2v_status build_psched(const PRecorder &rec, int dtype, int n_chain, int devic
   for (size_t i = 0; i < n; ++i) {
     const PRecord &r = rec.rec[i];
     const int c = r.chain;
+    if (c < 0 || c >= n_chain) {
+      set_error("sg2v_count_batch: a recorded launch names chain %d of %d", c, n_chain);
+      return SG2V_EINVAL;
+    }
     if (last[c] >= 0) {
       const PRecord &q = rec.rec[last[c]];
       const double rounds = std::ceil((double)q.gx * q.gy / (double)resident);
