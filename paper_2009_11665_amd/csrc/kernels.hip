@@ -1765,13 +1765,16 @@ __global__ void k_fill_value(T *X, int64_t count, T v) {
 // ===========================================================================
 // Persistent schedule: one kernel runs the recorded launches of several
 // independent chains (the templates of a batch).  Every virtual block of a
-// recorded launch is a task; a block of k_persist takes the next ticket,
-// waits (thread 0, bounded by a wall-clock limit) until the predecessor of
-// the ticket's launch in its chain has completed all of its tasks, runs the
-// launch's kernel body with the virtual block coordinates, and counts the
-// task as done.  Tickets are ordered so that every predecessor launch has
-// smaller tickets, and a ticket is only taken by a running block, so every
-// wait ends (by induction over the tickets) whatever the number of resident
+// recorded launch is a task; each chain numbers its tasks in launch order.
+// A block of k_persist looks for a chain whose next task can start (its
+// launch's predecessor has completed), else any chain with tasks left, takes
+// that chain's next ticket, waits if needed (thread 0, bounded by a
+// wall-clock limit) until the predecessor of the ticket's launch has
+// completed all of its tasks, runs the launch's kernel body with the virtual
+// block coordinates, and counts the task as done.  Within a chain every
+// predecessor launch has smaller tickets, a block holds one ticket at a time
+// and a ticket is only taken by a running block, so every wait ends (by
+// induction over each chain's tickets) whatever the number of resident
 // blocks.  Ordering across the XCDs: after a task every wave waits for its
 // stores, then one agent-scope release (L2 write-back) precedes the done
 // counter's increment; a block that has waited acquires at agent scope (L1
@@ -1996,21 +1999,53 @@ template <typename T>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) k_persist(PersistArgs p) {
   __shared__ long long s_t;
   __shared__ int s_cur;
-  __shared__ int s_seen[kPMaxChains];  // per chain: latest predecessor seen complete (thread 0)
-  for (int c = threadIdx.x; c < p.n_chain; c += BLOCK) s_seen[c] = -1;
-  int cur0 = 0;  // thread 0: launch of the block's last ticket (tickets only grow)
+  // thread 0 only, per chain: the latest predecessor seen complete, and the
+  // launch holding the chain's last ticket looked at (tickets only grow)
+  __shared__ int s_seen[kPMaxChains];
+  __shared__ int s_ccur[kPMaxChains];
+  for (int c = threadIdx.x; c < p.n_chain; c += BLOCK) {
+    s_seen[c] = -1;
+    s_ccur[c] = p.chain_first[c];
+  }
+  int home = (int)(blockIdx.x % (unsigned)p.n_chain);  // thread 0: chain looked at first
   for (;;) {
     __syncthreads();  // the previous task's reads of s_t and s_cur are done
     if (threadIdx.x == 0) {
       long long t = -1;
-      if (__hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        const unsigned long long q = atomicAdd(p.next, 1ull);
-        if ((long long)q < p.total) t = (long long)q;
+      int ch = -1;
+      // the first chain (from home) whose next task can start now, else the
+      // first with tasks left (the block then waits for its predecessor)
+      while (t < 0 && __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        int pick = -1, any = -1;
+        for (int i = 0; i < p.n_chain && pick < 0; ++i) {
+          const int c = (home + i) % p.n_chain;
+          const long long q = (long long)__hip_atomic_load(p.next + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (q >= p.chain_total[c]) continue;
+          if (any < 0) any = c;
+          int l = s_ccur[c];
+          while (l + 1 < p.chain_first[c + 1] && p.L[l + 1].first <= q) ++l;
+          s_ccur[c] = l;
+          const int pr = p.L[l].pred;
+          if (pr < 0 || s_seen[c] >= pr ||
+              __hip_atomic_load(p.done + pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)p.L[pr].ntask)
+            pick = c;
+        }
+        if (pick < 0) pick = any;
+        if (pick < 0) break;  // every chain handed out
+        const long long q = (long long)atomicAdd(p.next + pick, 1ull);
+        if (q < p.chain_total[pick]) {
+          t = q;
+          ch = pick;
+        }
       }
+      int cur = -1;
       if (t >= 0) {
-        while (cur0 + 1 < p.n_launch && p.L[cur0 + 1].first <= t) ++cur0;
-        const int pred = p.L[cur0].pred;
-        const int ch = p.L[cur0].chain;
+        home = ch;
+        int l = s_ccur[ch];
+        while (l + 1 < p.chain_first[ch + 1] && p.L[l + 1].first <= t) ++l;
+        s_ccur[ch] = l;
+        cur = l;
+        const int pred = p.L[cur].pred;
         if (pred >= 0 && s_seen[ch] < pred) {
           const unsigned need = (unsigned)p.L[pred].ntask;
           const long long t0 = wall_clock64();
@@ -2031,12 +2066,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8
         }
       }
       s_t = t;
-      s_cur = cur0;
+      s_cur = cur;
     }
     __syncthreads();
-    const long long t = s_t;
-    if (t < 0) break;  // uniform: every thread read s_t after the barrier
-    const int cur = s_cur;
+    // the same for every thread: read through the first lane so that the
+    // compiler treats the task (and the body's arguments) as wave-uniform
+    const long long st = s_t;
+    const long long t = (long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(st >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)st));
+    if (t < 0) break;
+    const int cur = __builtin_amdgcn_readfirstlane(s_cur);
     const PLaunch &L = p.L[cur];
     const long long vb = t - L.first;
     const VBlk bk{(unsigned)(vb % L.gx), (unsigned)(vb / L.gx), L.gx, L.gy};

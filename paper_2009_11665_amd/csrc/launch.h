@@ -290,10 +290,10 @@ void launch_zero_pad(int dtype, void *X, int64_t n, int64_t ld, int64_t c_from, 
 // append their launch (kernel body, grid, dynamic LDS and a copy of the
 // arguments) to it instead of issuing it; k_persist then runs the recorded
 // launches of several independent chains (one per template) in one kernel:
-// each virtual block of a launch is a task, tasks are handed out in ticket
-// order, and a task waits until its launch's predecessor in the same chain has
-// completed all of its tasks (a per-launch counter).  Launches that cannot run
-// there (other block sizes, multi-kernel launchers) set `err`.
+// each virtual block of a launch is a task, each chain hands out its tasks in
+// ticket order, and a task waits until its launch's predecessor in the same
+// chain has completed all of its tasks (a per-launch counter).  Launches that
+// cannot run there (other block sizes, multi-kernel launchers) set `err`.
 
 constexpr int kPArgBytes = 320;   // largest argument block (static_assert in kernels.hip)
 constexpr int kPMaxChains = 256;
@@ -304,7 +304,7 @@ struct PLaunch {
   int32_t pred;   // launch that must complete before this one starts (-1: none)
   uint32_t gx, gy;
   uint32_t pad;
-  int64_t first;  // ticket of the first virtual block
+  int64_t first;  // ticket (within its chain) of the first virtual block
   int64_t ntask;  // gx * gy
   alignas(16) unsigned char args[kPArgBytes];
 };
@@ -326,14 +326,15 @@ struct PRecorder {
 extern thread_local PRecorder *t_prec;
 
 struct PersistArgs {
-  const PLaunch *L;
+  const PLaunch *L;             // grouped by chain, in order within each chain
+  const int32_t *chain_first;   // [n_chain + 1]: first launch of each chain
+  const int64_t *chain_total;   // [n_chain]: tickets (virtual blocks) of each chain
   int32_t n_launch;
   int32_t n_chain;
-  int64_t total;             // tickets (virtual blocks of all launches)
-  unsigned *done;            // per launch: virtual blocks completed
-  unsigned long long *next;  // ticket counter
-  int *err;                  // set when a wait exceeded `timeout`
-  uint64_t timeout;          // wall-clock ticks a dependency wait may take
+  unsigned *done;               // per launch: virtual blocks completed
+  unsigned long long *next;     // per chain: ticket counter
+  int *err;                     // set when a wait exceeded `timeout`
+  uint64_t timeout;             // wall-clock ticks a dependency wait may take
 };
 
 // blocks of k_persist<dtype> one CU holds with `lds` bytes of dynamic LDS

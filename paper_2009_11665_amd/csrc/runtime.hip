@@ -2209,26 +2209,29 @@ extern "C" sg2v_status sg2v_debug_table(const sg2v_plan *plan, const sg2v_graph 
 namespace {
 
 // Recorded launches of a batch run by one k_persist launch: the host copy of
-// the launch table (in ticket order) and its device copy, the per-launch done
-// counters, the ticket counter and the error flag.
+// the launch table (grouped by chain) and its device copy followed by each
+// chain's ticket count and first launch; the control words: per-launch done
+// counters, per-chain ticket counters and the error flag.
 struct PSched {
   int dtype = 0;
   int n_chain = 1;
   size_t lds = 0;
   unsigned blocks = 0;
-  int64_t total = 0;
   uint64_t timeout = 0;
   std::vector<PLaunch> h;
-  PLaunch *d = nullptr;
-  unsigned *ctl = nullptr;  // done[n] | ticket counter (8 bytes, aligned) | error flag
+  std::vector<int64_t> chain_total;
+  std::vector<int32_t> chain_first;
+  char *d = nullptr;        // PLaunch[n] | int64 chain_total[n_chain] | int32 chain_first[n_chain + 1]
+  unsigned *ctl = nullptr;  // done[n] (padded to even) | uint64 next[n_chain] | error flag
   size_t ctl_words = 0;
   ~PSched() {
     if (d) (void)hipFree(d);
     if (ctl) (void)hipFree(ctl);
   }
+  size_t done_words() const { return (h.size() + 1) & ~(size_t)1; }
   unsigned *done() const { return ctl; }
-  unsigned long long *next() const { return (unsigned long long *)(ctl + ((h.size() + 1) & ~(size_t)1)); }
-  int *err() const { return (int *)(ctl + ((h.size() + 1) & ~(size_t)1) + 2); }
+  unsigned long long *next() const { return (unsigned long long *)(ctl + done_words()); }
+  int *err() const { return (int *)(ctl + done_words() + 2 * (size_t)n_chain); }
 };
 
 // One captured multi-template count: colourings of every plan plus all of
@@ -2263,96 +2266,85 @@ bool same_tuning(const sg2v_tuning_t &a, const sg2v_tuning_t &b) {
          a.xsplit_min == b.xsplit_min;
 }
 
-// Ticket order of the recorded launches: each chain's launches in order, a
-// launch's start estimated as its predecessor's start plus the predecessor's
-// rounds of resident blocks, launches sorted by that start (ties by chain),
-// so that independent chains interleave and every predecessor precedes its
-// successors.
+// The recorded launches grouped by chain (each chain's launches in recording
+// order, its tasks numbered from 0), each launch's predecessor the previous
+// launch of its chain.
 sg2v_status build_psched(const PRecorder &rec, int dtype, int n_chain, int device, PSched *ps) {
   const size_t n = rec.rec.size();
   if (n == 0) {
     set_error("sg2v_count_batch: nothing was recorded for the persistent schedule");
     return SG2V_EINVAL;
   }
-  if (n_chain > kPMaxChains) {
-    set_error("sg2v_count_batch: the persistent schedule runs at most %d templates", kPMaxChains);
+  if (n_chain < 1 || n_chain > kPMaxChains) {
+    set_error("sg2v_count_batch: the persistent schedule runs 1 to %d templates", kPMaxChains);
     return SG2V_EINVAL;
   }
   size_t lds = 0;
-  for (const PRecord &r : rec.rec) {
+  std::vector<std::vector<int>> of(n_chain);
+  for (size_t i = 0; i < n; ++i) {
+    const PRecord &r = rec.rec[i];
     if (r.dtype >= 0 && r.dtype != dtype) {
       set_error("sg2v_count_batch: a recorded launch has another element type");
       return SG2V_EINVAL;
     }
+    if (r.chain < 0 || r.chain >= n_chain) {
+      set_error("sg2v_count_batch: a recorded launch names chain %d of %d", r.chain, n_chain);
+      return SG2V_EINVAL;
+    }
     lds = std::max(lds, r.lds);
+    of[r.chain].push_back((int)i);
   }
-  hipDeviceProp_t prop;
-  HIP_TRY(hipGetDeviceProperties(&prop, device));
   const int per_cu = persist_blocks_per_cu(dtype, lds);
   if (per_cu < 1) {
     set_error("sg2v_count_batch: the persistent kernel does not fit a CU with %zu bytes of LDS", lds);
     return SG2V_ENOMEM;
   }
-  const int64_t resident = (int64_t)prop.multiProcessorCount * per_cu;
-  std::vector<double> start(n);
-  std::vector<int> prev(n, -1), last(n_chain, -1);
-  for (size_t i = 0; i < n; ++i) {
-    const PRecord &r = rec.rec[i];
-    const int c = r.chain;
-    if (c < 0 || c >= n_chain) {
-      set_error("sg2v_count_batch: a recorded launch names chain %d of %d", c, n_chain);
-      return SG2V_EINVAL;
-    }
-    if (last[c] >= 0) {
-      const PRecord &q = rec.rec[last[c]];
-      const double rounds = std::ceil((double)q.gx * q.gy / (double)resident);
-      start[i] = start[last[c]] + std::max(1.0, rounds);
-      prev[i] = last[c];
-    } else {
-      start[i] = 0.0;
-    }
-    last[c] = (int)i;
-  }
-  std::vector<int> order(n);
-  for (size_t i = 0; i < n; ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    if (start[a] != start[b]) return start[a] < start[b];
-    return rec.rec[a].chain < rec.rec[b].chain;
-  });
-  std::vector<int> pos(n);
-  for (size_t q = 0; q < n; ++q) pos[order[q]] = (int)q;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
   ps->h.assign(n, PLaunch{});
-  int64_t first = 0;
-  for (size_t q = 0; q < n; ++q) {
-    const PRecord &r = rec.rec[order[q]];
-    PLaunch &L = ps->h[q];
-    std::memset(&L, 0, sizeof(L));
-    L.body = r.body;
-    L.chain = r.chain;
-    L.pred = prev[order[q]] >= 0 ? pos[prev[order[q]]] : -1;
-    L.gx = r.gx;
-    L.gy = r.gy;
-    L.first = first;
-    L.ntask = (int64_t)r.gx * r.gy;
-    std::memcpy(L.args, r.args, kPArgBytes);
-    if (L.pred >= (int)q || L.ntask < 1 || L.ntask > (int64_t)UINT32_MAX) {
-      set_error("sg2v_count_batch: inconsistent persistent schedule");
-      return SG2V_EINVAL;
+  ps->chain_total.assign(n_chain, 0);
+  ps->chain_first.assign(n_chain + 1, 0);
+  int64_t all = 0;
+  size_t q = 0;
+  for (int c = 0; c < n_chain; ++c) {
+    ps->chain_first[c] = (int32_t)q;
+    int64_t first = 0;
+    for (size_t k = 0; k < of[c].size(); ++k, ++q) {
+      const PRecord &r = rec.rec[of[c][k]];
+      PLaunch &L = ps->h[q];
+      std::memset(&L, 0, sizeof(L));
+      L.body = r.body;
+      L.chain = c;
+      L.pred = k > 0 ? (int32_t)q - 1 : -1;
+      L.gx = r.gx;
+      L.gy = r.gy;
+      L.first = first;
+      L.ntask = (int64_t)r.gx * r.gy;
+      std::memcpy(L.args, r.args, kPArgBytes);
+      if (L.ntask < 1 || L.ntask > (int64_t)UINT32_MAX) {
+        set_error("sg2v_count_batch: a recorded launch has %lld blocks", (long long)L.ntask);
+        return SG2V_EINVAL;
+      }
+      first += L.ntask;
     }
-    first += L.ntask;
+    ps->chain_total[c] = first;
+    all += first;
   }
+  ps->chain_first[n_chain] = (int32_t)q;
   int clock_khz = 0;
   if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz <= 0)
     clock_khz = 100000;
   ps->dtype = dtype;
   ps->n_chain = n_chain;
   ps->lds = lds;
-  ps->blocks = (unsigned)std::min<int64_t>(resident, first);
-  ps->total = first;
+  ps->blocks = (unsigned)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, all);
   ps->timeout = (uint64_t)clock_khz * 1000ull * 30ull;  // 30 s per dependency wait
-  HIP_TRY(hipMalloc((void **)&ps->d, n * sizeof(PLaunch)));
-  HIP_TRY(hipMemcpy(ps->d, ps->h.data(), n * sizeof(PLaunch), hipMemcpyHostToDevice));
-  ps->ctl_words = ((n + 1) & ~(size_t)1) + 4;
+  const size_t lb = n * sizeof(PLaunch), tb = (size_t)n_chain * 8, fb = (size_t)(n_chain + 1) * 4;
+  HIP_TRY(hipMalloc((void **)&ps->d, lb + tb + fb));
+  HIP_TRY(hipMemcpy(ps->d, ps->h.data(), lb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ps->d + lb, ps->chain_total.data(), tb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ps->d + lb + tb, ps->chain_first.data(), fb, hipMemcpyHostToDevice));
+  ps->ctl_words = ps->done_words() + 2 * (size_t)n_chain + 2;
   HIP_TRY(hipMalloc((void **)&ps->ctl, ps->ctl_words * 4));
   return SG2V_OK;
 }
@@ -2360,10 +2352,12 @@ sg2v_status build_psched(const PRecorder &rec, int dtype, int n_chain, int devic
 void run_psched(const PSched &ps, hipStream_t s) {
   launch_fill_u32(ps.ctl, (int64_t)ps.ctl_words, 0u, s);
   PersistArgs a{};
-  a.L = ps.d;
+  const size_t lb = ps.h.size() * sizeof(PLaunch);
+  a.L = (const PLaunch *)ps.d;
+  a.chain_total = (const int64_t *)(ps.d + lb);
+  a.chain_first = (const int32_t *)(ps.d + lb + (size_t)ps.n_chain * 8);
   a.n_launch = (int32_t)ps.h.size();
   a.n_chain = ps.n_chain;
-  a.total = ps.total;
   a.done = ps.done();
   a.next = ps.next();
   a.err = ps.err();
