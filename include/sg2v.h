@@ -428,7 +428,11 @@ sg2v_status sg2v_profile_stop(sg2v_prof_entry_t *out);
                                           for their predecessor) instead of a HIP graph;
                                           implies SG2V_TUNE_NO_COLOR_EMA and
                                           SG2V_TUNE_ROOT_ROWS, and rejects
-                                          SG2V_TUNE_SPMM_PANEL with SG2V_EINVAL */
+                                          SG2V_TUNE_SPMM_PANEL with SG2V_EINVAL; a
+                                          wait longer than 30 s (or than the
+                                          environment's SG2V_PERSIST_WAIT_US
+                                          microseconds) stops the kernel and the
+                                          call returns SG2V_EDEVICE */
 #define SG2V_TUNE_SPMM_PANEL 1024 /* SpMM over row panels with column-sorted entries (the
                                      CSC-Split layout of Alg. 6): up to 32 consecutive tasks per
                                      panel, the panel's entries sorted by neighbour, one wave per

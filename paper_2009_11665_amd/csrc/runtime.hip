@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -2218,6 +2219,7 @@ struct PSched {
   size_t lds = 0;
   unsigned blocks = 0;
   uint64_t timeout = 0;
+  int clock_khz = 100000;  // device wall clock
   std::vector<PLaunch> h;
   std::vector<int64_t> chain_total;
   std::vector<int32_t> chain_first;
@@ -2338,6 +2340,7 @@ sg2v_status build_psched(const PRecorder &rec, int dtype, int n_chain, int devic
   ps->n_chain = n_chain;
   ps->lds = lds;
   ps->blocks = (unsigned)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, all);
+  ps->clock_khz = clock_khz;
   ps->timeout = (uint64_t)clock_khz * 1000ull * 30ull;  // 30 s per dependency wait
   const size_t lb = n * sizeof(PLaunch), tb = (size_t)n_chain * 8, fb = (size_t)(n_chain + 1) * 4;
   HIP_TRY(hipMalloc((void **)&ps->d, lb + tb + fb));
@@ -2362,6 +2365,10 @@ void run_psched(const PSched &ps, hipStream_t s) {
   a.next = ps.next();
   a.err = ps.err();
   a.timeout = ps.timeout;
+  // SG2V_PERSIST_WAIT_US: another bound on each dependency wait, in
+  // microseconds (tests of the time-out path)
+  if (const char *e = std::getenv("SG2V_PERSIST_WAIT_US"))
+    a.timeout = (uint64_t)std::strtoull(e, nullptr, 10) * (uint64_t)ps.clock_khz / 1000ull;
   launch_persist(ps.dtype, a, ps.blocks, ps.lds, s);
 }
 
@@ -2607,7 +2614,7 @@ extern "C" sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n
   if (hit->ps) HIP_TRY(hipMemcpyAsync(&perr, hit->ps->err(), 4, hipMemcpyDeviceToHost, us));
   HIP_TRY(hipStreamSynchronize(us));
   if (perr) {
-    set_error("sg2v_count_batch: a dependency wait of the persistent schedule exceeded 30 s");
+    set_error("sg2v_count_batch: a dependency wait of the persistent schedule timed out");
     return SG2V_EDEVICE;
   }
   for (int p = 0; p < n_plans; ++p)

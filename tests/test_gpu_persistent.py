@@ -115,3 +115,25 @@ def test_persistent_rejects_panel_spmm():
     plans = [sg.Plan(gg.BINTREE7)]
     with pytest.raises(RuntimeError, match="persistent"):
         _batch(plans, g, 1, 2, "u64", sg.TUNE_BATCH_PERSISTENT | sg.TUNE_SPMM_PANEL)
+
+
+def test_persistent_wait_timeout_reports_error(monkeypatch):
+    """A zero bound on the dependency waits, set from the host: a block that
+    finds its launch's predecessor unfinished raises the error flag, every
+    block stops taking tasks and the kernel ends normally; the call reports
+    the time-out, and the next call without the bound is exact."""
+    G = gg.chung_lu(20_000, 12.0, 2.1, seed=4)
+    g = sg.Graph.from_csr(G)
+    pars = (gg.BINTREE7, gg.PATH8)
+    plans = [sg.Plan(p) for p in pars]
+    seed, ncol = 3, 2
+    say("persistent time-out path")
+    monkeypatch.setenv("SG2V_PERSIST_WAIT_US", "0")
+    with pytest.raises(RuntimeError, match="timed out"):
+        _batch(plans, g, seed, ncol, "u64", sg.TUNE_BATCH_PERSISTENT)
+    monkeypatch.delenv("SG2V_PERSIST_WAIT_US")
+    cp, _ = _batch(plans, g, seed, ncol, "u64", sg.TUNE_BATCH_PERSISTENT)
+    for p, par in enumerate(pars):
+        for j in range(ncol):
+            u = O.count(G, par, len(par), O.colors(G.n, len(par), seed, j), mode=O.U64)[1]
+            assert cp[p][j] == float(u)
