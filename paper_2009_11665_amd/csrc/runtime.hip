@@ -68,7 +68,7 @@ struct TuneOr {
 };
 
 constexpr int64_t kSegment = 4096;  // neighbours per SpMM task (longer rows are split)
-constexpr int kPersistBlocks = 2048;
+constexpr int kSpmmBlocks = 2048;  // blocks of an SpMM launch without the split (grid stride over units)
 // blocks of an SpMM launch with the neighbour-range split (512 per XCD): more
 // than one round of resident blocks, so that the blocks of a range that finish
 // early pick up the remaining units (2048: 284 ms, 4096: 278 ms, 8192: 283 ms
@@ -1338,7 +1338,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
     pa.n = a.n;
     const int64_t per_launch = fl_launch_chunks();
     const int64_t gx = std::max<int64_t>(1, std::min<int64_t>((PN->n + 3) / 4,  // four waves per block
-                                                              kPersistBlocks));
+                                                              kSpmmBlocks));
     for (int64_t c0 = 0; c0 < chunks; c0 += per_launch) {
       const int64_t gc = std::min<int64_t>(per_launch, chunks - c0);
       const double frac = (double)gc / (double)chunks;
@@ -1358,7 +1358,7 @@ sg2v_status step_spmm(Ctx &x, int node) {
       const int64_t gc = std::min<int64_t>(per_launch, chunks - c0);
       const double frac = (double)gc / (double)chunks;
       a.chunk0 = c0;
-      dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)), (unsigned)gc);
+      dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kSpmmBlocks)), (unsigned)gc);
       ProfScope ps(SG2V_K_SPMM, bytes * frac, nnz * (double)nc * frac, x.s);
       if (launch_spmm(x.dt, a, x.pp.G, unroll, grid, x.s)) {
         set_error("sg2v_count: no SpMM variant for G=%d", x.pp.G);
@@ -2907,7 +2907,7 @@ sg2v_status count_grad_fp32s(const sg2v_plan *plan, sg2v_graph *gg, const sg2v_c
         a.n = g->n;
         a.nnz = g->nnz;
         const int64_t chunks = (cp + W - 1) / W;
-        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)), (unsigned)chunks);
+        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kSpmmBlocks)), (unsigned)chunks);
         {
           ProfScope ps(SG2V_K_SPMM, 2.0 * g->n * cp * 4 + (double)chunks * g->nnz * 8, (double)g->nnz * cp, s);
           if (launch_spmm(DT_F32, a, G, 4, grid, s)) {
@@ -3161,7 +3161,7 @@ sg2v_status count_grad_stored(const sg2v_plan *plan, const sg2v_graph *g, const 
         a.tsplit = nullptr;
         a.partial8 = nullptr;
         const int64_t chunks = (cp + W - 1) / W;
-        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kPersistBlocks)),
+        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(U->n_units, kSpmmBlocks)),
                   (unsigned)chunks);
         {
           ProfScope ps(SG2V_K_SPMM, 2.0 * g->n * cp * 8 + (double)chunks * g->nnz * 8,
