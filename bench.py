@@ -413,6 +413,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch-workload", action="store_true",
                     help="skip the multi-template batch and adjoint measurements")
+    ap.add_argument("--batch-only", choices=("graph", "graph-same", "persistent"), default=None,
+                    help="only run the batch workload's count twice in one mode (graph: the HIP "
+                         "graph with 128-column chunks; graph-same: the same with the persistent "
+                         "schedule's kernel choices; persistent: the persistent kernel) and exit "
+                         "(for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -428,6 +433,25 @@ def main():
 
     if args.traffic_from:
         write_traffic(*args.traffic_from, args.calibrate_copy or 1024, args.relabel)
+        return
+
+    if args.batch_only:
+        import torch
+        import graphgen as gg
+        import paper_2009_11665_amd as sg
+        G = gg.chung_lu_500k()
+        g = sg.Graph.from_csr(G)
+        plans = [sg.Plan(sg.reroot(p, len(p), 0.05)[0]) for p in (gg.BINTREE7, gg.PATH8, gg.CATERPILLAR10)]
+        flags = sg.TUNE_NO_COLOR_SKIP
+        if args.batch_only != "graph":
+            flags |= sg.TUNE_NO_COLOR_EMA | sg.TUNE_ROOT_ROWS
+        if args.batch_only == "persistent":
+            flags |= sg.TUNE_BATCH_PERSISTENT
+        with sg.tuned(flags=flags, spmm_width=128):
+            for _ in range(2):
+                sg.count_batch(plans, g, 4, 16, "fp32s")
+        torch.cuda.synchronize()
+        print(json.dumps({"batch_only": args.batch_only, "runs": 2}))
         return
 
     if args.calibrate_gather:
