@@ -1777,7 +1777,8 @@ __global__ void k_fill_value(T *X, int64_t count, T v) {
 // induction over each chain's tickets) whatever the number of resident
 // blocks.  Ordering across the XCDs: after a task every wave waits for its
 // stores, then one agent-scope release (L2 write-back) precedes the done
-// counter's increment; a block that has waited acquires at agent scope (L1
+// counter's increment; a block that starts a launch whose predecessor it
+// has not yet seen complete waits for it, then acquires at agent scope (L1
 // and L2 invalidate) before any of its threads reads; a block remembers per
 // chain the latest predecessor it has seen complete, so it waits and
 // acquires once per launch boundary.
