@@ -137,3 +137,23 @@ def test_persistent_wait_timeout_reports_error(monkeypatch):
         for j in range(ncol):
             u = O.count(G, par, len(par), O.colors(G.n, len(par), seed, j), mode=O.U64)[1]
             assert cp[p][j] == float(u)
+
+
+def test_persistent_many_chains():
+    """All 23 trees of eight vertices as one batch (23 chains, one per
+    template): U64 counts equal the graph-recorded batch's and, for three
+    of them, the oracle's."""
+    G = gg.rmat(10, 6_000, seed=12)
+    g = sg.Graph.from_csr(G)
+    pars = sg.trees(8)
+    assert len(pars) == 23
+    plans = [sg.Plan(p) for p in pars]
+    seed, ncol = 6, 2
+    say("persistent 23 chains")
+    cp, _ = _batch(plans, g, seed, ncol, "u64", sg.TUNE_BATCH_PERSISTENT)
+    cg, _ = _batch(plans, g, seed, ncol, "u64", 0)
+    np.testing.assert_array_equal(cp, cg)
+    for p in (0, 11, 22):
+        par = pars[p]
+        u = O.count(G, par, len(par), O.colors(G.n, len(par), seed, 1), mode=O.U64)[1]
+        assert cp[p][1] == float(u)
