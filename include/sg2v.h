@@ -322,8 +322,13 @@ sg2v_status sg2v_estimate(const sg2v_plan *plan, const sg2v_graph *g, uint64_t s
 
 /* Several templates over n_colorings colourings each (colourings
  * seed-derived per plan: sg2v_color(g, k_p, seed, 0, n_colorings)), run as
- * one captured device graph.  colorful/estimate: n_plans x n_colorings,
- * plan-major, host.  Errors as sg2v_count. */
+ * one captured device graph (the templates as parallel branches when their
+ * workspaces fit half of the free device memory), or, with the tuning flag
+ * SG2V_TUNE_BATCH_PERSISTENT, as one persistent kernel over every template's
+ * recorded launches.  The graph or schedule is cached and replayed by later
+ * calls with the same arguments.  colorful/estimate: n_plans x n_colorings,
+ * plan-major, host.  Errors as sg2v_count; EDEVICE also when a dependency
+ * wait of the persistent schedule times out. */
 sg2v_status sg2v_count_batch(const sg2v_plan *const *plans, int32_t n_plans,
                              const sg2v_graph *g, uint64_t seed, int32_t n_colorings,
                              sg2v_mode mode, void *stream, double *colorful, double *estimate);
